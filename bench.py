@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""Benchmark of the ACE hot path on one MI355X.
+
+One step = reset the count arrays, insert every point (hash + count update),
+score every point (hash + gather-sum), compute the mean/std threshold and flag
+the points below it: the whole of Alg. 1 plus the Sec. 5.3 threshold over one
+synthetic batch that is already resident in HBM.
+
+Workload: connection-log shaped points, 494,021 x 120 (38 lognormal columns,
+82 one-hot columns, 20% anomalies from rare clusters), K = 15 bits, L = 50
+tables, FP32 projections refined in FP64 inside the FP32 error bound.
+
+Prints one JSON line (see the keys below).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
+
+
+def cpu_baseline(X, W, K, L, target_s=12.0):
+    """The oracle, untuned, on a bounded prefix of the workload: hash + insert every sample
+    row, then hash + score every sample row.  Returns points/s of that sample."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def run(m):
+        t0 = time.perf_counter()
+        c, _ = oracle.hash_codes(X[:m], W, K, L)
+        sk = oracle.Sketch(K, L)
+        sk.insert_codes(c)
+        c2, _ = oracle.hash_codes(X[:m], W, K, L)
+        T = sk.score_codes(c2)
+        rc, th = sk.threshold(oracle.MODE_SCORED, 1.0)
+        sk.flags(T, th["tau"], oracle.MODE_SCORED)
+        return time.perf_counter() - t0
+
+    m = 2000
+    t = run(m)
+    m2 = int(min(X.shape[0], max(m, m * target_s / max(t, 1e-3))))
+    t2 = run(m2)
+    return {"value": m2 / t2, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m2} of {X.shape[0]} rows, hash+insert then hash+score+threshold, "
+                      f"{t2:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout "
+              f"is a design, not a run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from ace_inputs import c2_points, projection_matrix
+    from paper_1706_06664_amd import ACE
+
+    K, L, d = 15, 50, 120
+    X, _ = c2_points()
+    n = X.shape[0]
+    W = projection_matrix(d, K, L, 1706066642)
+    dev = torch.device("cuda", 0)
+    Xd = torch.from_numpy(X).to(dev)
+    s = torch.empty(n, dtype=torch.float32, device=dev)
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    ace = ACE(W, K, L, precision="fp32", device=0)
+
+    def step():
+        ace.reset()
+        ace.insert(Xd)
+        ace.score(Xd, s=s, T=T)
+        th = ace.threshold("scored", 1.0)
+        return ace.flag(T, th["tau"], "scored"), th
+
+    print(f"[bench] warmup {args.warmup} steps, n={n}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ace.profile()  # discard
+    ace.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        flags, th = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ace.profile_enable(False)
+    prof = ace.profile()
+    cnt = ace.counters()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    hash_avg_ms = prof["hash_ms"] / max(1, prof["hash_launches"])
+    rows_per_launch = prof["hash_rows"] / max(1, prof["hash_launches"])
+    flop_per_launch = 2.0 * rows_per_launch * d * K * L
+    achieved = flop_per_launch / (hash_avg_ms / 1e3)
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK["fp32"], "traffic": None,
+            "kernel": "hash_fp32_kernel (projection + sign-pack + FP64 refine)",
+            "avg_launch_ms": hash_avg_ms, "rows_per_launch": rows_per_launch}
+    phases = {k: prof[k] / args.steps for k in ("hash_ms", "update_ms", "score_ms", "other_ms")}
+
+    base = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        base = cpu_baseline(X, W, K, L)
+
+    out = {
+        "metric": "points/s insert+score (K=15,L=50)",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "connection-log 494021x120, K=15, L=50, FP32 + FP64 refine",
+                   "n": n, "d": d, "K": K, "L": L, "precision": "fp32", "refine": True},
+        "roofline": roof,
+        "cpu_baseline": base,
+        "phase_ms_per_step": phases,
+        "refined_bit_frac": cnt["bits_refined"] / max(1, cnt["bits_hashed"]),
+        "flagged": int(flags.sum().item()),
+        "tau": th["tau"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

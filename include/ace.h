@@ -1,0 +1,217 @@
+/*
+ * ace.h - C ABI of the ACE hot path on AMD Instinct MI355X (gfx950).
+ *
+ * ACE ("Arrays of (locality-sensitive) Count Estimators", Luo & Shrivastava,
+ * arXiv 1706.06664) keeps L arrays of 2^K counters.  Every point x is hashed
+ * by K*L signed random projections (Sec. 2.1: bit = sign(w^T x), w ~ N(0, I)),
+ * the K bits of table j are concatenated into a code H_j(x) (Sec. 3.2), and
+ *   insert:  A_j[H_j(x)] += 1 for every j             (Alg. 1, counting phase)
+ *   score:   s(q) = (1/L) sum_j A_j[H_j(q)]           (Alg. 1, query phase)
+ *   mean:    mu = mean score of the inserted points, kept exactly from the
+ *            counts (Sec. 3.4.1, Eq. dynadd / Eq. dynsub)
+ *   report:  s(q) <= mu - alpha (Alg. 1), or s(q) < mu_s - sigma_s over the
+ *            scored set (Sec. 5.3).
+ *
+ * Conventions used by every call:
+ *   - W is given once at create time, on the host: FP32, [d][K*L] row-major;
+ *     column c = j*K + k is the projection vector of bit k of table j.  The
+ *     library copies it; the caller may free it after ace_create returns.
+ *   - Bit = 1 iff w^T x > 0 (a zero projection gives 0).  Bit k of a code is
+ *     the bit of column j*K + k.
+ *   - X: FP32, [n][d] row-major, in device memory, owned by the caller.  Rows
+ *     must be finite, with ||x|| * ||w_c|| below 2^100 for every column (so
+ *     FP32 accumulation cannot overflow).
+ *   - Device output buffers are owned by the caller and must hold n entries
+ *     (or the documented shape).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream only enqueue work and return; calls on one
+ *     context must be ordered by the caller (one stream, or events), because
+ *     they share the context's counts and workspace.
+ *   - Argument and overflow errors are returned before anything is enqueued
+ *     and leave the context unchanged.  A device error is sticky: the call
+ *     that sees it and every later call on the context return ACE_E_DEVICE;
+ *     destroy the context and rebuild it (ace_set_counts restores a saved
+ *     state).
+ *   - A context is not thread-safe.
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ace_ctx_s* ace_ctx;
+
+typedef enum {
+    ACE_OK = 0,
+    ACE_E_INVALID = 1,   /* bad argument; nothing enqueued */
+    ACE_E_NOMEM = 2,     /* device allocation failed or would exceed mem_budget */
+    ACE_E_OVERFLOW = 3,  /* the call would overflow a 32-bit counter or score */
+    ACE_E_EMPTY = 4,     /* threshold asked of an empty set */
+    ACE_E_DEVICE = 5,    /* a HIP call or kernel failed (sticky) */
+    ACE_E_STATE = 6      /* the call does not fit the context's state (e.g. deleting from an empty bucket) */
+} ace_status;
+
+typedef enum {
+    ACE_FP32 = 0,        /* FP32 inputs on FP32 MFMA, FP32 accumulate */
+    ACE_BF16 = 1,        /* BF16 split operands on BF16 MFMA, FP32 accumulate */
+    ACE_FP8E4M3 = 2      /* e4m3 operands with power-of-two row/column scales on FP8 MFMA, FP32 accumulate */
+} ace_precision;
+
+typedef enum {
+    ACE_THR_SCORED = 0,  /* tau = mu_s - alpha sigma_s of the scored set; report s < tau (Sec. 5.3) */
+    ACE_THR_CONST = 1,   /* tau = mu - alpha; report s <= tau (Alg. 1) */
+    ACE_THR_TABLE = 2    /* tau = mu - alpha sigma_table; report s < tau */
+} ace_thr_mode;
+
+typedef struct {
+    int32_t d;               /* input dimension, >= 1 */
+    int32_t K;               /* bits per table, 1..16 */
+    int32_t L;               /* tables, 1..4096 */
+    int32_t precision;       /* ace_precision */
+    int32_t refine;          /* 1 (default): every projection whose low-precision value lies
+                                inside its derived error bound is recomputed in FP64 from the
+                                FP32 inputs, so every bit equals sign of the FP64 sum;
+                                0: raw low-precision signs (for flip-rate reports) */
+    int32_t device;          /* HIP device ordinal */
+    int64_t max_batch_rows;  /* rows hashed per internal chunk; 0 = 1<<20 */
+    int64_t mem_budget;      /* device bytes the context may allocate; 0 = unlimited */
+} ace_config;
+
+/* Result of ace_threshold (all scores are s = T / L). */
+typedef struct {
+    int64_t n;               /* points currently inserted */
+    int64_t m_scored;        /* points scored since the last reset of the scored set */
+    double mu;               /* mean score of the inserted points = sum_j S2_j / (n L) */
+    double mu_scored;        /* mean score of the scored set */
+    double sigma;            /* population std of the scored set's scores */
+    double sigma_table;      /* (1/L) sum_j std over inserted points of A_j[H_j(x)] */
+    double tau;              /* threshold of the requested mode */
+    int32_t mode;
+    int32_t pad;
+} ace_thresh;
+
+/* Running counters of a context. */
+typedef struct {
+    int64_t n;               /* points currently inserted */
+    int64_t m_scored;        /* points in the scored set */
+    int64_t sum_T;           /* sum of T over the scored set */
+    uint64_t sum_T2_lo;      /* sum of T^2 over the scored set, unsigned 128-bit */
+    uint64_t sum_T2_hi;
+    uint64_t bits_hashed;    /* projection bits computed (rows * K * L) */
+    uint64_t bits_refined;   /* bits recomputed in FP64 */
+    uint64_t bits_flipped;   /* refined bits whose sign differed from the low-precision sign */
+} ace_counters;
+
+/* Create a context on cfg->device: copies W (host, FP32 [d][K*L]) and zeroes the L x 2^K
+ * int32 counts.  Returns ACE_E_INVALID for out-of-range fields or NULL pointers,
+ * ACE_E_NOMEM if allocation fails or exceeds cfg->mem_budget, ACE_E_DEVICE if the
+ * device cannot be used.  *out is set only on success. */
+ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out);
+
+/* Synchronise the device and free everything the context owns.  NULL is a no-op. */
+ace_status ace_destroy(ace_ctx ctx);
+
+/* Zero the counts, the per-table sums and the scored set (stream-ordered). */
+ace_status ace_reset(ace_ctx ctx, void* stream);
+
+/* Zero only the scored set's moments (stream-ordered). */
+ace_status ace_reset_scored(ace_ctx ctx, void* stream);
+
+/* Counting phase of Alg. 1: hash the n rows of X_dev and add each to its bucket in every
+ * table; the per-table sums S2_j = sum_b A_j[b]^2 (which give mu, Eq. dynadd) and
+ * S3_j = sum_b A_j[b]^3 are updated exactly.  n = 0 is a no-op.  ACE_E_OVERFLOW if the
+ * total would exceed INT32_MAX points. */
+ace_status ace_insert(ace_ctx ctx, const float* X_dev, int64_t n, void* stream);
+
+/* Deletion of Sec. 3.4.1 (Eq. dynsub): hash the rows and subtract each from its bucket in
+ * every table.  The rows must have been inserted before; a bucket that would go below
+ * zero leaves the context in error state ACE_E_STATE (sticky). */
+ace_status ace_delete(ace_ctx ctx, const float* X_dev, int64_t n, void* stream);
+
+/* Query phase of Alg. 1: T(q) = sum_j A_j[H_j(q)], s = T / L, for the n rows of X_dev.
+ * s_dev (FP32 [n]) and T_dev (uint32 [n]) may each be NULL.  The rows join the scored
+ * set (m, sum T, sum T^2).  ACE_E_OVERFLOW if L * n_inserted could exceed UINT32_MAX. */
+ace_status ace_score(ace_ctx ctx, const float* X_dev, int64_t n, float* s_dev, uint32_t* T_dev,
+                     void* stream);
+
+/* Threshold of Alg. 1 / Sec. 5.3 in the given mode with parameter alpha.  Enqueues the
+ * reduction on `stream`, waits for it and fills *out (host).  ACE_E_EMPTY if the mode's
+ * set is empty (no inserted points, or no scored points for ACE_THR_SCORED). */
+ace_status ace_threshold(ace_ctx ctx, int32_t mode, double alpha, void* stream, ace_thresh* out);
+
+/* flags_dev[i] = 1 iff s_i = T_dev[i] / L is reported: s < tau for ACE_THR_SCORED and
+ * ACE_THR_TABLE, s <= tau for ACE_THR_CONST.  uint8 [n]. */
+ace_status ace_flag(ace_ctx ctx, const uint32_t* T_dev, int64_t n, double tau, int32_t mode,
+                    uint8_t* flags_dev, void* stream);
+
+/* Hash only: codes_dev receives uint16 [L][n] (table-major: code of row i in table j at
+ * j*n + i).  refined_dev (same shape, may be NULL) receives, per code, the mask of bits that
+ * were recomputed in FP64.  Does not touch the counts. */
+ace_status ace_hash(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_dev,
+                    uint16_t* refined_dev, void* stream);
+
+/* Counting phase from precomputed codes (uint16 [L][n] device, values < 2^K). */
+ace_status ace_insert_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, void* stream);
+
+/* Query phase from precomputed codes (uint16 [L][n] device). */
+ace_status ace_score_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, float* s_dev,
+                           uint32_t* T_dev, void* stream);
+
+/* Copy the counts to the host: int32 [L][2^K].  Synchronises the device. */
+ace_status ace_get_counts(ace_ctx ctx, int32_t* counts_host);
+
+/* Copy the exact per-table sums to the host: S2 int64 [L], S3 uint64 [L][2] (lo, hi of an
+ * unsigned 128-bit integer).  Synchronises the device. */
+ace_status ace_get_table_stats(ace_ctx ctx, int64_t* S2_host, uint64_t* S3_host);
+
+/* Copy the running counters to the host.  Synchronises the device. */
+ace_status ace_get_counters(ace_ctx ctx, ace_counters* out);
+
+/* Restore a saved state: counts int32 [L][2^K] (host) describing n inserted points.  S2 and
+ * S3 are recomputed from the counts on the device; the scored set is cleared.  ACE_E_INVALID
+ * if a count is negative or a table does not sum to n.  Synchronises the device. */
+ace_status ace_set_counts(ace_ctx ctx, const int32_t* counts_host, int64_t n);
+
+/* Per-kernel timing of a context, from HIP events recorded on the launch stream around
+ * every kernel launch while profiling is on. */
+typedef struct {
+    double hash_ms;          /* projection + sign-pack (+ refine) kernels */
+    int64_t hash_launches;
+    int64_t hash_rows;       /* rows hashed by those launches */
+    double update_ms;        /* insert / delete count updates */
+    int64_t update_launches;
+    double score_ms;         /* gather-sum scoring */
+    int64_t score_launches;
+    double other_ms;         /* threshold, flags, zeroing */
+    int64_t other_launches;
+} ace_profile;
+
+/* Turn event timing on (1) or off (0).  While on, each launch records two events on its
+ * stream; the cost is a few microseconds per launch. */
+ace_status ace_profile_enable(ace_ctx ctx, int32_t on);
+
+/* Synchronise the device, resolve the recorded events into *out and clear them. */
+ace_status ace_get_profile(ace_ctx ctx, ace_profile* out);
+
+/* Human-readable name of a status. */
+const char* ace_status_string(ace_status s);
+
+/* Library version string. */
+const char* ace_version(void);
+
+/* Test hooks, for exercising error paths from the host.  ace_debug_fail_next makes the next
+ * enqueueing call report a device failure (the sticky ACE_E_DEVICE path) without launching
+ * anything; ace_debug_set_capacity lowers the INT32_MAX insert cap so ACE_E_OVERFLOW can be
+ * reached with small inputs (0 restores the default). */
+ace_status ace_debug_fail_next(ace_ctx ctx);
+ace_status ace_debug_set_capacity(ace_ctx ctx, int64_t max_points);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H */

@@ -1,0 +1,266 @@
+"""Thin Python binding of the ACE C ABI (argument marshalling only).
+
+Every step of the path runs in the HIP library `libace_hip.so`; PyTorch is
+used only to own device memory and to name streams.  There is no fallback:
+if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libace_hip.so")
+
+FP32, BF16, FP8E4M3 = 0, 1, 2
+THR_SCORED, THR_CONST, THR_TABLE = 0, 1, 2
+_PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "e4m3": FP8E4M3}
+_MODES = {"scored": THR_SCORED, "const": THR_CONST, "table": THR_TABLE}
+
+STATUS = {0: "ACE_OK", 1: "ACE_E_INVALID", 2: "ACE_E_NOMEM", 3: "ACE_E_OVERFLOW", 4: "ACE_E_EMPTY",
+          5: "ACE_E_DEVICE", 6: "ACE_E_STATE"}
+
+# Every symbol include/ace.h declares.
+EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_insert", "ace_delete", "ace_score",
+           "ace_threshold", "ace_flag", "ace_hash", "ace_insert_codes", "ace_score_codes", "ace_get_counts",
+           "ace_get_table_stats", "ace_get_counters", "ace_set_counts", "ace_status_string", "ace_version",
+           "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile"]
+
+
+class AceError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("refine", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("max_batch_rows", ctypes.c_int64), ("mem_budget", ctypes.c_int64)]
+
+
+class Thresh(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m_scored", ctypes.c_int64), ("mu", ctypes.c_double),
+                ("mu_scored", ctypes.c_double), ("sigma", ctypes.c_double), ("sigma_table", ctypes.c_double),
+                ("tau", ctypes.c_double), ("mode", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("hash_ms", ctypes.c_double), ("hash_launches", ctypes.c_int64), ("hash_rows", ctypes.c_int64),
+                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64),
+                ("score_ms", ctypes.c_double), ("score_launches", ctypes.c_int64),
+                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m_scored", ctypes.c_int64), ("sum_T", ctypes.c_int64),
+                ("sum_T2_lo", ctypes.c_uint64), ("sum_T2_hi", ctypes.c_uint64), ("bits_hashed", ctypes.c_uint64),
+                ("bits_refined", ctypes.c_uint64), ("bits_flipped", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"ACE HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sigs = {
+        "ace_create": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
+        "ace_destroy": [P],
+        "ace_reset": [P, P],
+        "ace_reset_scored": [P, P],
+        "ace_insert": [P, P, i64, P],
+        "ace_delete": [P, P, i64, P],
+        "ace_score": [P, P, i64, P, P, P],
+        "ace_threshold": [P, i32, f64, P, ctypes.POINTER(Thresh)],
+        "ace_flag": [P, P, i64, f64, i32, P, P],
+        "ace_hash": [P, P, i64, P, P, P],
+        "ace_insert_codes": [P, P, i64, P],
+        "ace_score_codes": [P, P, i64, P, P, P],
+        "ace_get_counts": [P, P],
+        "ace_get_table_stats": [P, P, P],
+        "ace_get_counters": [P, ctypes.POINTER(Counters)],
+        "ace_set_counts": [P, P, i64],
+        "ace_debug_fail_next": [P],
+        "ace_debug_set_capacity": [P, i64],
+        "ace_profile_enable": [P, i32],
+        "ace_get_profile": [P, ctypes.POINTER(Profile)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ace_status_string.argtypes = [ctypes.c_int]
+    lib.ace_status_string.restype = ctypes.c_char_p
+    lib.ace_version.argtypes = []
+    lib.ace_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise AceError(rc, where)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, dtype, what: str):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor")
+    return t.data_ptr()
+
+
+class ACE:
+    """L count arrays of 2^K counters on one GPU, filled and queried through the C ABI."""
+
+    def __init__(self, W: np.ndarray, K: int, L: int, precision: str = "fp32", refine: bool = True,
+                 device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0):
+        import torch
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        if W.ndim != 2 or W.shape[1] != K * L:
+            raise ValueError("W must be float32 [d][K*L]")
+        self.lib = load_library()
+        self.d, self.K, self.L = int(W.shape[0]), int(K), int(L)
+        self.device = torch.device("cuda", device)
+        cfg = Config(self.d, self.K, self.L, _PREC[precision], 1 if refine else 0, device, max_batch_rows,
+                     mem_budget)
+        h = ctypes.c_void_p()
+        _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+               "ace_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ace_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- stream-ordered calls ---
+    def reset(self, stream=None):
+        _check(self.lib.ace_reset(self.h, _stream_ptr(stream)), "ace_reset")
+
+    def reset_scored(self, stream=None):
+        _check(self.lib.ace_reset_scored(self.h, _stream_ptr(stream)), "ace_reset_scored")
+
+    def _rows(self, X):
+        import torch
+        if X.dim() != 2 or X.shape[1] != self.d:
+            raise ValueError(f"X must be [n][{self.d}]")
+        return _dev_ptr(X, torch.float32, "X"), X.shape[0]
+
+    def insert(self, X, stream=None):
+        p, n = self._rows(X)
+        _check(self.lib.ace_insert(self.h, p, n, _stream_ptr(stream)), "ace_insert")
+
+    def delete(self, X, stream=None):
+        p, n = self._rows(X)
+        _check(self.lib.ace_delete(self.h, p, n, _stream_ptr(stream)), "ace_delete")
+
+    def score(self, X, s=None, T=None, want_s: bool = True, want_T: bool = True, stream=None):
+        import torch
+        p, n = self._rows(X)
+        if want_s and s is None:
+            s = torch.empty(n, dtype=torch.float32, device=X.device)
+        if want_T and T is None:
+            T = torch.empty(n, dtype=torch.int32, device=X.device)
+        _check(self.lib.ace_score(self.h, p, n, _dev_ptr(s, torch.float32, "s"), _dev_ptr(T, torch.int32, "T"),
+                                  _stream_ptr(stream)), "ace_score")
+        return s, T
+
+    def hash(self, X, want_refined: bool = False, stream=None):
+        """Codes as an int16 tensor [L][n] holding the uint16 bit patterns."""
+        import torch
+        p, n = self._rows(X)
+        codes = torch.empty((self.L, n), dtype=torch.int16, device=X.device)
+        ref = torch.empty((self.L, n), dtype=torch.int16, device=X.device) if want_refined else None
+        _check(self.lib.ace_hash(self.h, p, n, codes.data_ptr(), ref.data_ptr() if ref is not None else None,
+                                 _stream_ptr(stream)), "ace_hash")
+        return (codes, ref) if want_refined else codes
+
+    def insert_codes(self, codes, stream=None):
+        import torch
+        assert codes.dim() == 2 and codes.shape[0] == self.L
+        _check(self.lib.ace_insert_codes(self.h, _dev_ptr(codes, torch.int16, "codes"), codes.shape[1],
+                                         _stream_ptr(stream)), "ace_insert_codes")
+
+    def score_codes(self, codes, stream=None):
+        import torch
+        n = codes.shape[1]
+        s = torch.empty(n, dtype=torch.float32, device=codes.device)
+        T = torch.empty(n, dtype=torch.int32, device=codes.device)
+        _check(self.lib.ace_score_codes(self.h, _dev_ptr(codes, torch.int16, "codes"), n, s.data_ptr(),
+                                        T.data_ptr(), _stream_ptr(stream)), "ace_score_codes")
+        return s, T
+
+    def threshold(self, mode="scored", alpha: float = 1.0, stream=None) -> dict:
+        m = _MODES[mode] if isinstance(mode, str) else int(mode)
+        out = Thresh()
+        _check(self.lib.ace_threshold(self.h, m, float(alpha), _stream_ptr(stream), ctypes.byref(out)),
+               "ace_threshold")
+        return {f: getattr(out, f) for f, _ in Thresh._fields_ if f != "pad"}
+
+    def flag(self, T, tau: float, mode="scored", stream=None):
+        import torch
+        m = _MODES[mode] if isinstance(mode, str) else int(mode)
+        flags = torch.empty(T.shape[0], dtype=torch.uint8, device=T.device)
+        _check(self.lib.ace_flag(self.h, _dev_ptr(T, torch.int32, "T"), T.shape[0], float(tau), m,
+                                 flags.data_ptr(), _stream_ptr(stream)), "ace_flag")
+        return flags
+
+    # --- synchronising getters ---
+    def counts(self) -> np.ndarray:
+        out = np.empty((self.L, 1 << self.K), np.int32)
+        _check(self.lib.ace_get_counts(self.h, out.ctypes.data_as(ctypes.c_void_p)), "ace_get_counts")
+        return out
+
+    def table_stats(self):
+        S2 = np.empty(self.L, np.int64)
+        S3 = np.empty((self.L, 2), np.uint64)
+        _check(self.lib.ace_get_table_stats(self.h, S2.ctypes.data_as(ctypes.c_void_p),
+                                            S3.ctypes.data_as(ctypes.c_void_p)), "ace_get_table_stats")
+        return S2, S3
+
+    def counters(self) -> dict:
+        out = Counters()
+        _check(self.lib.ace_get_counters(self.h, ctypes.byref(out)), "ace_get_counters")
+        return {f: getattr(out, f) for f, _ in Counters._fields_}
+
+    def profile_enable(self, on: bool = True):
+        _check(self.lib.ace_profile_enable(self.h, 1 if on else 0), "ace_profile_enable")
+
+    def profile(self) -> dict:
+        out = Profile()
+        _check(self.lib.ace_get_profile(self.h, ctypes.byref(out)), "ace_get_profile")
+        return {f: getattr(out, f) for f, _ in Profile._fields_}
+
+    def set_counts(self, counts: np.ndarray, n: int):
+        counts = np.ascontiguousarray(counts, np.int32)
+        _check(self.lib.ace_set_counts(self.h, counts.ctypes.data_as(ctypes.c_void_p), int(n)), "ace_set_counts")
+
+
+def codes_as_uint16(codes_t) -> np.ndarray:
+    """Device int16 codes [L][n] -> host uint16 [n][L] (the row-major layout the oracle uses)."""
+    return codes_t.cpu().numpy().view(np.uint16).T.copy()

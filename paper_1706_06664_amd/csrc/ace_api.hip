@@ -1,0 +1,612 @@
+// Host side of the ACE C ABI: validation, device state, chunking and launches.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ace_internal.h"
+
+using namespace ace;
+
+struct ace_ctx_s {
+    ace_config cfg;
+    int TW = 5;            // tables per wave in the projection kernel
+    int n_tiles_n = 1;     // column tiles
+    int NP = 0;            // padded columns allocated (n_tiles_n * 32 * TW)
+    int DP = 0;            // padded contraction length
+    float gx = 0.f, eps_abs = 0.f;
+
+    float* Wt = nullptr;   // [NP][DP]
+    float* wb = nullptr;   // [NP]
+    int32_t* counts = nullptr;   // [L][2^K]
+    u64* S2 = nullptr;           // [L]
+    u64* S3 = nullptr;           // [L][2]
+    u64* mom = nullptr;          // m, sum T, sum T^2 lo, hi
+    u64* rcnt = nullptr;         // bits refined, bits flipped
+    unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
+    DevThresh* thr = nullptr;
+    uint16_t* ws_codes = nullptr;  // [L][ws_rows]
+    int64_t ws_rows = 0;
+
+    int64_t n_total = 0;
+    int64_t cap = INT32_MAX;
+    u64 bits_hashed = 0;
+    size_t bytes = 0;
+    ace_status sticky = ACE_OK;
+    int fail_next = 0;
+
+    // Event timing: pairs of (start, end, class) recorded while profiling is on.
+    int profiling = 0;
+    struct Timed { hipEvent_t a, b; int cls; int64_t rows; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+ace_status dev_alloc(ace_ctx c, void** p, size_t bytes) {
+    if (c->cfg.mem_budget > 0 && c->bytes + bytes > (size_t)c->cfg.mem_budget) return ACE_E_NOMEM;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return ACE_E_NOMEM;
+    }
+    c->bytes += bytes;
+    return ACE_OK;
+}
+
+enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3 };
+
+hipEvent_t take_event(ace_ctx c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Bracket one launch with events when profiling is on.
+struct Bracket {
+    ace_ctx c;
+    hipStream_t s;
+    int cls;
+    int64_t rows;
+    hipEvent_t a = nullptr;
+    Bracket(ace_ctx c_, hipStream_t s_, int cls_, int64_t rows_ = 0) : c(c_), s(s_), cls(cls_), rows(rows_) {
+        if (c->profiling) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Bracket() {
+        if (a) {
+            hipEvent_t b = take_event(c);
+            if (b && hipEventRecord(b, s) == hipSuccess) c->timed.push_back({a, b, cls, rows});
+            else c->pool.push_back(a);
+        }
+    }
+};
+
+void free_all(ace_ctx c) {
+    for (auto& t : c->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    c->timed.clear();
+    c->pool.clear();
+    void* ptrs[] = {c->Wt, c->wb, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+// Record a launch result: a failed launch makes the context sticky.
+ace_status check(ace_ctx c, hipError_t e) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->sticky = ACE_E_DEVICE;
+        return ACE_E_DEVICE;
+    }
+    return ACE_OK;
+}
+
+ace_status enter(ace_ctx c) {
+    if (!c) return ACE_E_INVALID;
+    if (c->sticky != ACE_OK) return c->sticky;
+    return ACE_OK;
+}
+
+// A debug hook turns the next enqueueing call into a device failure.
+bool take_injected_failure(ace_ctx c) {
+    if (c->fail_next) {
+        c->fail_next = 0;
+        c->sticky = ACE_E_DEVICE;
+        return true;
+    }
+    return false;
+}
+
+int pick_tw(int L) {
+    // Fewest padded tables; ties go to the wider tile.
+    const int cand[] = {5, 4, 8, 2, 1};
+    int best = 5;
+    long best_pad = -1;
+    for (int tw : cand) {
+        const long tiles = (L + 2 * tw - 1) / (2 * tw);
+        const long pad = tiles * 2 * tw - L;
+        if (best_pad < 0 || pad < best_pad) {
+            best_pad = pad;
+            best = tw;
+        }
+    }
+    return best;
+}
+
+// Hash rows [0, n) of X (one chunk of at most ws_rows rows) into codes[j*ldc + i].
+ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, uint16_t* codes, int64_t ldc, uint16_t* refined,
+                      hipStream_t s) {
+    HashArgs a;
+    a.X = X;
+    a.n = n;
+    a.d = c->cfg.d;
+    a.Wt = c->Wt;
+    a.DP = c->DP;
+    a.wb = c->wb;
+    a.L = c->cfg.L;
+    a.K = c->cfg.K;
+    a.n_tiles_n = c->n_tiles_n;
+    a.n_tiles_m = (n + 127) / 128;
+    a.gx = c->gx;
+    a.eps_abs = c->eps_abs;
+    a.refine = c->cfg.refine;
+    a.codes = codes;
+    a.ldc = ldc;
+    a.refined = refined;
+    a.counters = c->rcnt;
+    const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
+    c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
+    Bracket br(c, s, CLS_HASH, n);
+    return check(c, launch_hash_fp32(a, c->TW, vec, s));
+}
+
+ace_status update_rows(ace_ctx c, const float* X, int64_t n, int sign, hipStream_t s) {
+    for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
+        const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
+        ace_status st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, c->ws_codes, m, nullptr, s);
+        if (st != ACE_OK) return st;
+        {
+            Bracket br(c, s, CLS_UPDATE, m);
+            st = check(c, launch_count_update(c->ws_codes, m, m, c->cfg.K, c->cfg.L, sign, c->counts, c->S2, c->S3,
+                                              c->err, s));
+        }
+        if (st != ACE_OK) return st;
+    }
+    return ACE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ace_status_string(ace_status s) {
+    switch (s) {
+        case ACE_OK: return "ACE_OK";
+        case ACE_E_INVALID: return "ACE_E_INVALID";
+        case ACE_E_NOMEM: return "ACE_E_NOMEM";
+        case ACE_E_OVERFLOW: return "ACE_E_OVERFLOW";
+        case ACE_E_EMPTY: return "ACE_E_EMPTY";
+        case ACE_E_DEVICE: return "ACE_E_DEVICE";
+        case ACE_E_STATE: return "ACE_E_STATE";
+        default: return "ACE_E_UNKNOWN";
+    }
+}
+
+const char* ace_version(void) { return "ace-mi355x 0.1 (gfx950)"; }
+
+ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) {
+    if (!cfg || !W_host || !out) return ACE_E_INVALID;
+    if (cfg->d < 1 || cfg->K < 1 || cfg->K > 16 || cfg->L < 1 || cfg->L > 4096) return ACE_E_INVALID;
+    if (cfg->precision != ACE_FP32) return ACE_E_INVALID;
+    if (cfg->refine != 0 && cfg->refine != 1) return ACE_E_INVALID;
+    if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
+    if ((int64_t)cfg->d > (int64_t)1 << 24) return ACE_E_INVALID;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device >= ndev) {
+        (void)hipGetLastError();
+        return ACE_E_DEVICE;
+    }
+    DeviceGuard g(cfg->device);
+    if (!g.ok) return ACE_E_DEVICE;
+    static bool attrs_done = false;
+    if (!attrs_done) {
+        if (init_kernel_attributes() != hipSuccess) {
+            (void)hipGetLastError();
+            return ACE_E_DEVICE;
+        }
+        attrs_done = true;
+    }
+
+    ace_ctx c = new (std::nothrow) ace_ctx_s();
+    if (!c) return ACE_E_NOMEM;
+    c->cfg = *cfg;
+    if (c->cfg.max_batch_rows == 0) c->cfg.max_batch_rows = (int64_t)1 << 20;
+    const int d = cfg->d, K = cfg->K, L = cfg->L;
+    c->TW = pick_tw(L);
+    c->n_tiles_n = (L + 2 * c->TW - 1) / (2 * c->TW);
+    c->NP = c->n_tiles_n * 32 * c->TW;
+    c->DP = (d + DPAD - 1) / DPAD * DPAD;
+    // gamma_h(2^-23) with h = 2d + 8, rounded up by a relative 2^-16 for the FP32 bound product.
+    const double u = ldexp(1.0, -23), h = 2.0 * d + 8.0;
+    c->gx = (float)(h * u / (1.0 - h * u) * (1.0 + ldexp(1.0, -16)));
+    c->eps_abs = (float)(h * ldexp(1.0, -125));
+    c->ws_rows = c->cfg.max_batch_rows;
+
+    const int64_t B = (int64_t)1 << K;
+    ace_status st = ACE_OK;
+    st = st ? st : dev_alloc(c, (void**)&c->Wt, sizeof(float) * (size_t)c->NP * c->DP);
+    st = st ? st : dev_alloc(c, (void**)&c->wb, sizeof(float) * (size_t)c->NP);
+    st = st ? st : dev_alloc(c, (void**)&c->counts, sizeof(int32_t) * (size_t)L * B);
+    st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
+    st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
+    st = st ? st : dev_alloc(c, (void**)&c->mom, sizeof(u64) * 4);
+    st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 2);
+    st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
+    st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
+    st = st ? st : dev_alloc(c, (void**)&c->ws_codes, sizeof(uint16_t) * (size_t)L * c->ws_rows);
+    if (st != ACE_OK) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    // Padded device copy of W: column cp = j*16 + k holds w_{jK+k}; zero elsewhere.
+    std::vector<float> Wt((size_t)c->NP * c->DP, 0.f);
+    std::vector<float> wb((size_t)c->NP, -1.f);
+    for (int j = 0; j < L; ++j)
+        for (int k = 0; k < K; ++k) {
+            const int cp = j * KPAD + k;
+            double ss = 0.0;
+            for (int t = 0; t < d; ++t) {
+                const float w = W_host[(size_t)t * K * L + (size_t)j * K + k];
+                Wt[(size_t)cp * c->DP + t] = w;
+                ss += (double)w * (double)w;
+            }
+            wb[cp] = (float)(sqrt(ss) * (1.0 + ldexp(1.0, -20)));
+        }
+    hipError_t e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->wb, wb.data(), wb.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->counts, 0, sizeof(int32_t) * (size_t)L * B);
+    if (e == hipSuccess) e = hipMemset(c->S2, 0, sizeof(u64) * (size_t)L);
+    if (e == hipSuccess) e = hipMemset(c->S3, 0, sizeof(u64) * 2 * (size_t)L);
+    if (e == hipSuccess) e = hipMemset(c->mom, 0, sizeof(u64) * 4);
+    if (e == hipSuccess) e = hipMemset(c->rcnt, 0, sizeof(u64) * 2);
+    if (e == hipSuccess) e = hipMemset(c->err, 0, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_all(c);
+        delete c;
+        return ACE_E_DEVICE;
+    }
+    *out = c;
+    return ACE_OK;
+}
+
+ace_status ace_destroy(ace_ctx c) {
+    if (!c) return ACE_OK;
+    DeviceGuard g(c->cfg.device);
+    (void)hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+    return ACE_OK;
+}
+
+ace_status ace_reset(ace_ctx c, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    Bracket br(c, s, CLS_OTHER);
+    const size_t cb = sizeof(int32_t) * (size_t)c->cfg.L << c->cfg.K;
+    st = check(c, launch_zero(c->counts, cb, s));
+    if (!st) st = check(c, launch_zero(c->S2, sizeof(u64) * (size_t)c->cfg.L, s));
+    if (!st) st = check(c, launch_zero(c->S3, sizeof(u64) * 2 * (size_t)c->cfg.L, s));
+    if (!st) st = check(c, launch_zero(c->mom, sizeof(u64) * 4, s));
+    if (!st) c->n_total = 0;
+    return st;
+}
+
+ace_status ace_reset_scored(ace_ctx c, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    return check(c, launch_zero(c->mom, sizeof(u64) * 4, (hipStream_t)stream));
+}
+
+ace_status ace_insert(ace_ctx c, const float* X, int64_t n, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !X)) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if (c->n_total + n > c->cap) return ACE_E_OVERFLOW;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    st = update_rows(c, X, n, +1, (hipStream_t)stream);
+    if (!st) c->n_total += n;
+    return st;
+}
+
+ace_status ace_delete(ace_ctx c, const float* X, int64_t n, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !X)) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if (n > c->n_total) return ACE_E_STATE;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    st = update_rows(c, X, n, -1, (hipStream_t)stream);
+    if (!st) c->n_total -= n;
+    return st;
+}
+
+ace_status ace_insert_codes(ace_ctx c, const uint16_t* codes, int64_t n, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !codes)) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if (c->n_total + n > c->cap) return ACE_E_OVERFLOW;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    st = check(c, launch_count_update(codes, n, n, c->cfg.K, c->cfg.L, +1, c->counts, c->S2, c->S3, c->err,
+                                      (hipStream_t)stream));
+    if (!st) c->n_total += n;
+    return st;
+}
+
+static ace_status score_guard(ace_ctx c) {
+    // T = sum of L counts, each <= n_total, must fit uint32.
+    if ((u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull) return ACE_E_OVERFLOW;
+    return ACE_OK;
+}
+
+ace_status ace_score(ace_ctx c, const float* X, int64_t n, float* s_out, uint32_t* T_out, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !X)) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if ((st = score_guard(c))) return st;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
+        const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
+        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, c->ws_codes, m, nullptr, s);
+        if (st) return st;
+        {
+            Bracket br(c, s, CLS_SCORE, m);
+            st = check(c, launch_score(c->ws_codes, m, m, c->cfg.K, c->cfg.L, c->counts, s_out ? s_out + r0 : nullptr,
+                                       T_out ? T_out + r0 : nullptr, c->mom, s));
+        }
+        if (st) return st;
+    }
+    return ACE_OK;
+}
+
+ace_status ace_score_codes(ace_ctx c, const uint16_t* codes, int64_t n, float* s_out, uint32_t* T_out,
+                           void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !codes)) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if ((st = score_guard(c))) return st;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    return check(c, launch_score(codes, n, n, c->cfg.K, c->cfg.L, c->counts, s_out, T_out, c->mom,
+                                 (hipStream_t)stream));
+}
+
+ace_status ace_hash(ace_ctx c, const float* X, int64_t n, uint16_t* codes, uint16_t* refined, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!X || !codes))) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
+        const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
+        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, codes + r0, n, refined ? refined + r0 : nullptr, s);
+        if (st) return st;
+    }
+    return ACE_OK;
+}
+
+ace_status ace_threshold(ace_ctx c, int32_t mode, double alpha, void* stream, ace_thresh* out) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!out || mode < 0 || mode > 2 || !isfinite(alpha)) return ACE_E_INVALID;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Bracket br(c, s, CLS_OTHER);
+        st = check(c, launch_threshold(c->n_total, c->cfg.L, c->S2, c->S3, c->mom, mode, alpha, c->thr, s));
+    }
+    if (st) return st;
+    DevThresh r;
+    unsigned errs[4];
+    hipError_t e = hipMemcpyAsync(&r, c->thr, sizeof(r), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(errs, c->err, sizeof(errs), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((st = check(c, e))) return st;
+    if (errs[0]) {
+        c->sticky = ACE_E_STATE;
+        return ACE_E_STATE;
+    }
+    out->n = r.n;
+    out->m_scored = r.m_scored;
+    out->mu = r.mu;
+    out->mu_scored = r.mu_scored;
+    out->sigma = r.sigma;
+    out->sigma_table = r.sigma_table;
+    out->tau = r.tau;
+    out->mode = r.mode;
+    out->pad = 0;
+    return r.status ? (ace_status)r.status : ACE_OK;
+}
+
+ace_status ace_flag(ace_ctx c, const uint32_t* T, int64_t n, double tau, int32_t mode, uint8_t* flags, void* stream) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (n < 0 || mode < 0 || mode > 2 || !isfinite(tau) || (n > 0 && (!T || !flags))) return ACE_E_INVALID;
+    if (n == 0) return ACE_OK;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    Bracket br(c, (hipStream_t)stream, CLS_OTHER);
+    return check(c, launch_flags(T, n, c->cfg.L, tau, mode, flags, (hipStream_t)stream));
+}
+
+static ace_status sync_and_check(ace_ctx c) {
+    hipError_t e = hipDeviceSynchronize();
+    ace_status st = check(c, e);
+    if (st) return st;
+    unsigned errs[4];
+    if ((st = check(c, hipMemcpy(errs, c->err, sizeof(errs), hipMemcpyDeviceToHost)))) return st;
+    if (errs[0]) {
+        c->sticky = ACE_E_STATE;
+        return ACE_E_STATE;
+    }
+    return ACE_OK;
+}
+
+ace_status ace_get_counts(ace_ctx c, int32_t* host) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!host) return ACE_E_INVALID;
+    DeviceGuard g(c->cfg.device);
+    if ((st = sync_and_check(c))) return st;
+    return check(c, hipMemcpy(host, c->counts, sizeof(int32_t) * ((size_t)c->cfg.L << c->cfg.K), hipMemcpyDeviceToHost));
+}
+
+ace_status ace_get_table_stats(ace_ctx c, int64_t* S2_host, uint64_t* S3_host) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!S2_host || !S3_host) return ACE_E_INVALID;
+    DeviceGuard g(c->cfg.device);
+    if ((st = sync_and_check(c))) return st;
+    st = check(c, hipMemcpy(S2_host, c->S2, sizeof(u64) * (size_t)c->cfg.L, hipMemcpyDeviceToHost));
+    if (st) return st;
+    return check(c, hipMemcpy(S3_host, c->S3, sizeof(u64) * 2 * (size_t)c->cfg.L, hipMemcpyDeviceToHost));
+}
+
+ace_status ace_get_counters(ace_ctx c, ace_counters* out) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!out) return ACE_E_INVALID;
+    DeviceGuard g(c->cfg.device);
+    if ((st = sync_and_check(c))) return st;
+    u64 mom[4], r[2];
+    st = check(c, hipMemcpy(mom, c->mom, sizeof(mom), hipMemcpyDeviceToHost));
+    if (!st) st = check(c, hipMemcpy(r, c->rcnt, sizeof(r), hipMemcpyDeviceToHost));
+    if (st) return st;
+    out->n = c->n_total;
+    out->m_scored = (int64_t)mom[0];
+    out->sum_T = (int64_t)mom[1];
+    out->sum_T2_lo = mom[2];
+    out->sum_T2_hi = mom[3];
+    out->bits_hashed = c->bits_hashed;
+    out->bits_refined = r[0];
+    out->bits_flipped = r[1];
+    return ACE_OK;
+}
+
+ace_status ace_set_counts(ace_ctx c, const int32_t* host, int64_t n) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!host || n < 0 || n > c->cap) return ACE_E_INVALID;
+    const int64_t B = (int64_t)1 << c->cfg.K;
+    for (int j = 0; j < c->cfg.L; ++j) {
+        int64_t sum = 0;
+        for (int64_t b = 0; b < B; ++b) {
+            if (host[(int64_t)j * B + b] < 0) return ACE_E_INVALID;
+            sum += host[(int64_t)j * B + b];
+        }
+        if (sum != n) return ACE_E_INVALID;
+    }
+    DeviceGuard g(c->cfg.device);
+    if ((st = sync_and_check(c))) return st;
+    st = check(c, hipMemcpy(c->counts, host, sizeof(int32_t) * (size_t)c->cfg.L * B, hipMemcpyHostToDevice));
+    if (!st) st = check(c, launch_table_sums(c->counts, c->cfg.K, c->cfg.L, c->S2, c->S3, nullptr));
+    if (!st) st = check(c, launch_zero(c->mom, sizeof(u64) * 4, nullptr));
+    if (!st) st = check(c, hipDeviceSynchronize());
+    if (!st) c->n_total = n;
+    return st;
+}
+
+ace_status ace_profile_enable(ace_ctx c, int32_t on) {
+    if (!c) return ACE_E_INVALID;
+    c->profiling = on ? 1 : 0;
+    return ACE_OK;
+}
+
+ace_status ace_get_profile(ace_ctx c, ace_profile* out) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!out) return ACE_E_INVALID;
+    DeviceGuard g(c->cfg.device);
+    if ((st = check(c, hipDeviceSynchronize()))) return st;
+    memset(out, 0, sizeof(*out));
+    for (auto& t : c->timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) {
+            (void)hipGetLastError();
+            ms = 0.f;
+        }
+        switch (t.cls) {
+            case CLS_HASH: out->hash_ms += ms; out->hash_launches++; out->hash_rows += t.rows; break;
+            case CLS_UPDATE: out->update_ms += ms; out->update_launches++; break;
+            case CLS_SCORE: out->score_ms += ms; out->score_launches++; break;
+            default: out->other_ms += ms; out->other_launches++; break;
+        }
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->timed.clear();
+    return ACE_OK;
+}
+
+ace_status ace_debug_fail_next(ace_ctx c) {
+    if (!c) return ACE_E_INVALID;
+    c->fail_next = 1;
+    return ACE_OK;
+}
+
+ace_status ace_debug_set_capacity(ace_ctx c, int64_t max_points) {
+    if (!c || max_points < 0) return ACE_E_INVALID;
+    c->cap = max_points == 0 ? (int64_t)INT32_MAX : max_points;
+    return ACE_OK;
+}
+
+}  // extern "C"

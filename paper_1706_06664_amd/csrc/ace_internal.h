@@ -1,0 +1,63 @@
+// Internal declarations shared by the host API and the kernels of the ACE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ace.h"
+
+namespace ace {
+
+typedef unsigned long long u64;
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+// Columns per table in the padded projection layout: every table owns 16
+// consecutive columns (bits k >= K are zero columns), so one 16-wide MFMA
+// output tile is exactly one table.
+constexpr int KPAD = 16;
+// Contraction padding of the device copy of W.
+constexpr int DPAD = 32;
+
+// Arguments of the projection + sign-pack kernels (one per precision).
+struct HashArgs {
+    const float* X;        // [n][d] FP32, caller's device memory
+    int64_t n;
+    int32_t d;
+    const float* Wt;       // [NP][DP] FP32: padded column cp = j*16 + k holds w_{jK+k}
+    int32_t DP;
+    const float* wb;       // [NP] column bound factor (norm of w, rounded up); < 0 for pad columns
+    int32_t L, K;
+    int32_t n_tiles_n;     // column tiles (each 32*TW padded columns)
+    int64_t n_tiles_m;     // row tiles
+    float gx;              // row bound factor: gamma * safety
+    float eps_abs;         // absolute term for flushed subnormals
+    int32_t refine;
+    uint16_t* codes;       // [L][ldc]: code of row i of this chunk in table j at j*ldc + i
+    int64_t ldc;
+    uint16_t* refined;     // same layout or null: mask of bits recomputed in FP64
+    u64* counters;         // [0] bits refined, [1] refined bits that flipped
+};
+
+// Device-side threshold result (mirrors ace_thresh).
+struct DevThresh {
+    int64_t n, m_scored;
+    double mu, mu_scored, sigma, sigma_table, tau;
+    int32_t mode, status;
+};
+
+// Launchers (enqueue only; return the launch error).
+hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
+// sign = +1 insert, -1 delete
+hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
+                               int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s);
+hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const int32_t* counts,
+                        float* s_out, uint32_t* T_out, u64* mom, hipStream_t s);
+hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode,
+                            double alpha, DevThresh* out, hipStream_t s);
+hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);
+hipError_t launch_table_sums(const int32_t* counts, int K, int L, u64* S2, u64* S3, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t init_kernel_attributes();
+
+}  // namespace ace

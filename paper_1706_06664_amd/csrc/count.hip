@@ -1,0 +1,355 @@
+// Count arrays, scores and the threshold (Alg. 1; Sec. 3.4.1 Eq. dynadd / dynsub; Sec. 5.3).
+//
+// Counts are int32 [L][2^K] in device memory.  Alongside them the library keeps
+// S2_j = sum_b A_j[b]^2 (int64) and S3_j = sum_b A_j[b]^3 (unsigned 128-bit, two
+// u64 words), exactly.  An update that moves a count from `old` to `new` adds
+// new^2 - old^2 and new^3 - old^3; atomics return `old`, so the deltas telescope to
+// the exact sums whatever the order of the updates.  sum_j S2_j / (n L) is the mean
+// score of the inserted points (Eq. dynadd / dynsub with the pre-update count).
+//
+// The scored set keeps m, sum T and sum T^2 (128-bit) exactly in the same way, so
+// the threshold's mean and variance come from exact integers.
+#include "ace_internal.h"
+
+namespace ace {
+
+namespace {
+
+__device__ inline u64 wave_sum_u64(u64 v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline void wave_sum_u128(u64& lo, u64& hi) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const u64 olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
+        const u64 nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+    }
+}
+
+__device__ inline void atomic_add_u128(u64* p, u64 lo, u64 hi) {
+    const u64 old = atomicAdd(p, lo);
+    const u64 carry = (old + lo < old) ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(p + 1, hi + carry);
+}
+
+// Block-wide sum of (a, b_lo, b_hi) with a 64-bit plain sum and a 128-bit pair; the
+// results are valid in thread 0.  `scratch` holds 3 * (blockDim/64) u64.
+__device__ inline void block_sum3(u64& a, u64& lo, u64& hi, u64* scratch) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_sum_u64(a);
+    wave_sum_u128(lo, hi);
+    if (lane == 0) {
+        scratch[3 * wave] = a;
+        scratch[3 * wave + 1] = lo;
+        scratch[3 * wave + 2] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+            a += scratch[3 * w];
+            const u64 nlo = lo + scratch[3 * w + 1];
+            hi += scratch[3 * w + 2] + (nlo < lo ? 1ull : 0ull);
+            lo = nlo;
+        }
+    }
+}
+
+// Exact change of (count^2, count^3) when a count moves from `old` by `delta`.
+__device__ inline void sq_cube_delta(int64_t old, int64_t delta, u64& d2, u64& d3lo, u64& d3hi) {
+    const i128 o = old, nw = old + delta;
+    const i128 dd2 = nw * nw - o * o;
+    const i128 dd3 = nw * nw * nw - o * o * o;
+    d2 = (u64)(int64_t)dd2;
+    const u128 u3 = (u128)dd3;
+    d3lo = (u64)u3;
+    d3hi = (u64)(u3 >> 64);
+}
+
+__device__ inline void add128(u64& lo, u64& hi, u64 alo, u64 ahi) {
+    const u64 nlo = lo + alo;
+    hi += ahi + (nlo < lo ? 1ull : 0ull);
+    lo = nlo;
+}
+
+constexpr int HIST_THREADS = 1024;
+
+// LDS-privatised histogram update of one table over a chunk of rows.
+// Grid: (chunks, L).  K <= 15: one uint32 LDS counter per bucket (<= 128 KB).
+// K == 16: two uint16 counters per uint32 word (128 KB), chunk <= 65535 rows.
+template <bool PACK16>
+__global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t* __restrict__ codes, int64_t ldc,
+                                                                  int64_t n, int64_t rows_per_block, int K, int sign,
+                                                                  int32_t* __restrict__ counts, u64* __restrict__ S2,
+                                                                  u64* __restrict__ S3, unsigned* __restrict__ err) {
+    extern __shared__ uint32_t hist[];
+    __shared__ u64 red[3 * (HIST_THREADS / 64)];
+    const int j = blockIdx.y;
+    const int64_t B = (int64_t)1 << K;
+    const int64_t words = PACK16 ? (B >> 1) : B;
+    for (int64_t w = threadIdx.x; w < words; w += blockDim.x) hist[w] = 0u;
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    const uint16_t* cj = codes + (int64_t)j * ldc;
+    const uint32_t bmask = (uint32_t)(B - 1);  // codes from callers are reduced to K bits
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const uint32_t b = cj[i] & bmask;
+        if (PACK16)
+            atomicAdd(&hist[b >> 1], 1u << (16 * (b & 1)));
+        else
+            atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    u64 s2 = 0, s3lo = 0, s3hi = 0;
+    int32_t* cnt = counts + (int64_t)j * B;
+    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+        const uint32_t h = PACK16 ? ((hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu) : hist[b];
+        if (h) {
+            const int32_t delta = sign > 0 ? (int32_t)h : -(int32_t)h;
+            const int32_t old = atomicAdd(&cnt[b], delta);
+            if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+            u64 d2, d3lo, d3hi;
+            sq_cube_delta(old, delta, d2, d3lo, d3hi);
+            s2 += d2;
+            add128(s3lo, s3hi, d3lo, d3hi);
+        }
+    }
+    block_sum3(s2, s3lo, s3hi, red);
+    if (threadIdx.x == 0) {
+        if (s2) atomicAdd(&S2[j], s2);
+        atomic_add_u128(&S3[2 * j], s3lo, s3hi);
+    }
+}
+
+// Direct update for small batches: one thread per (row, table), one global atomic each.
+// Grid: (ceil(n/256), L).
+__global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __restrict__ codes, int64_t ldc,
+                                                            int64_t n, int K, int sign, int32_t* __restrict__ counts,
+                                                            u64* __restrict__ S2, u64* __restrict__ S3,
+                                                            unsigned* __restrict__ err) {
+    __shared__ u64 red[3 * 4];
+    const int j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 s2 = 0, s3lo = 0, s3hi = 0;
+    if (i < n) {
+        const uint32_t b = codes[(int64_t)j * ldc + i] & ((1u << K) - 1u);
+        const int32_t delta = sign > 0 ? 1 : -1;
+        const int32_t old = atomicAdd(&counts[((int64_t)j << K) + b], delta);
+        if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+        sq_cube_delta(old, delta, s2, s3lo, s3hi);
+    }
+    block_sum3(s2, s3lo, s3hi, red);
+    if (threadIdx.x == 0) {
+        if (s2) atomicAdd(&S2[j], s2);
+        atomic_add_u128(&S3[2 * j], s3lo, s3hi);
+    }
+}
+
+// Query phase: T(q) = sum_j A_j[H_j(q)], s = T / L; one thread per row.  The block's
+// (m, sum T, sum T^2) are added to the scored-set moments mom[0..3].
+__global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__ codes, int64_t ldc, int64_t n,
+                                                    int K, int L, const int32_t* __restrict__ counts,
+                                                    float* __restrict__ s_out, uint32_t* __restrict__ T_out,
+                                                    u64* __restrict__ mom) {
+    __shared__ u64 red[3 * 4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t T = 0;
+    const bool ok = i < n;
+    if (ok) {
+        const uint16_t* c = codes + i;
+        const int32_t* a = counts;
+        const uint32_t bm = (1u << K) - 1u;  // codes from callers are reduced to K bits
+        int j = 0;
+        for (; j + 4 <= L; j += 4) {
+            const uint32_t b0 = c[(int64_t)j * ldc] & bm, b1 = c[(int64_t)(j + 1) * ldc] & bm;
+            const uint32_t b2 = c[(int64_t)(j + 2) * ldc] & bm, b3 = c[(int64_t)(j + 3) * ldc] & bm;
+            const uint32_t v0 = (uint32_t)a[((int64_t)j << K) + b0];
+            const uint32_t v1 = (uint32_t)a[((int64_t)(j + 1) << K) + b1];
+            const uint32_t v2 = (uint32_t)a[((int64_t)(j + 2) << K) + b2];
+            const uint32_t v3 = (uint32_t)a[((int64_t)(j + 3) << K) + b3];
+            T += (v0 + v1) + (v2 + v3);
+        }
+        for (; j < L; ++j) T += (uint32_t)a[((int64_t)j << K) + (c[(int64_t)j * ldc] & bm)];
+        if (s_out) s_out[i] = (float)((double)T / (double)L);
+        if (T_out) T_out[i] = T;
+    }
+    u64 sT = ok ? (u64)T : 0ull;
+    const u128 t2 = ok ? (u128)T * (u128)T : (u128)0;
+    u64 lo = (u64)t2, hi = (u64)(t2 >> 64);
+    block_sum3(sT, lo, hi, red);
+    if (threadIdx.x == 0) {
+        const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+        const int64_t m = min((int64_t)blockDim.x, n - r0);
+        atomicAdd(&mom[0], (u64)m);
+        atomicAdd(&mom[1], sT);
+        atomic_add_u128(&mom[2], lo, hi);
+    }
+}
+
+// Threshold statistics from the exact sums (one thread).
+__device__ inline double u128_to_double(u64 lo, u64 hi) { return (double)hi * 0x1p64 + (double)lo; }
+
+__global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, const u64* __restrict__ S3,
+                                 const u64* __restrict__ mom, int mode, double alpha, DevThresh* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevThresh r;
+    r.n = n;
+    r.m_scored = (int64_t)mom[0];
+    r.mode = mode;
+    r.status = 0;
+    i128 s2tot = 0;
+    for (int j = 0; j < L; ++j) s2tot += (i128)(int64_t)S2[j];
+    r.mu = n > 0 ? (double)(int64_t)s2tot / ((double)n * (double)L) : 0.0;
+    const int64_t m = (int64_t)mom[0];
+    const int64_t sumT = (int64_t)mom[1];
+    r.mu_scored = 0.0;
+    r.sigma = 0.0;
+    if (m > 0) {
+        const u128 st2 = ((u128)mom[3] << 64) | mom[2];
+        const i128 num = (i128)m * (i128)st2 - (i128)sumT * (i128)sumT;
+        const u128 un = (u128)num;
+        r.mu_scored = (double)sumT / ((double)m * (double)L);
+        r.sigma = sqrt(u128_to_double((u64)un, (u64)(un >> 64))) / ((double)m * (double)L);
+    }
+    r.sigma_table = 0.0;
+    if (n > 0) {
+        double acc = 0.0;
+        for (int j = 0; j < L; ++j) {
+            const u128 s3 = ((u128)S3[2 * j + 1] << 64) | S3[2 * j];
+            const i128 s2 = (i128)(int64_t)S2[j];
+            const i128 v = (i128)n * (i128)s3 - s2 * s2;
+            const u128 uv = (u128)v;
+            acc += sqrt(u128_to_double((u64)uv, (u64)(uv >> 64))) / (double)n;
+        }
+        r.sigma_table = acc / (double)L;
+    }
+    r.tau = 0.0;
+    if (mode == ACE_THR_SCORED) {
+        if (m == 0) r.status = ACE_E_EMPTY;
+        else r.tau = r.mu_scored - alpha * r.sigma;
+    } else if (mode == ACE_THR_CONST) {
+        if (n == 0) r.status = ACE_E_EMPTY;
+        else r.tau = r.mu - alpha;
+    } else {
+        if (n == 0) r.status = ACE_E_EMPTY;
+        else r.tau = r.mu - alpha * r.sigma_table;
+    }
+    *out = r;
+}
+
+__global__ __launch_bounds__(256) void flags_kernel(const uint32_t* __restrict__ T, int64_t n, double lim, int le,
+                                                    uint8_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double t = (double)T[i];
+    flags[i] = (uint8_t)(le ? (t <= lim) : (t < lim));
+}
+
+// S2_j and S3_j recomputed from the counts (checkpoint restore).  Grid: L blocks.
+__global__ __launch_bounds__(256) void table_sums_kernel(const int32_t* __restrict__ counts, int K,
+                                                         u64* __restrict__ S2, u64* __restrict__ S3) {
+    __shared__ u64 red[3 * 4];
+    const int j = blockIdx.x;
+    const int64_t B = (int64_t)1 << K;
+    u64 s2 = 0, lo = 0, hi = 0;
+    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+        const int64_t a = counts[(int64_t)j * B + b];
+        s2 += (u64)(a * a);
+        const u128 c = (u128)(a * a) * (u128)a;
+        add128(lo, hi, (u64)c, (u64)(c >> 64));
+    }
+    block_sum3(s2, lo, hi, red);
+    if (threadIdx.x == 0) {
+        S2[j] = s2;
+        S3[2 * j] = lo;
+        S3[2 * j + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace
+
+hipError_t init_kernel_attributes() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&update_lds_kernel<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&update_lds_kernel<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+}
+
+hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
+                               int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t B = (int64_t)1 << K;
+    // The LDS histogram pays one scan of 2^K buckets per block; use it when a block
+    // sees at least 2^K / 2 rows, otherwise one global atomic per (row, table).
+    if (n < B / 2) {
+        const int64_t nb = (n + 255) / 256;
+        hipLaunchKernelGGL(update_direct_kernel, dim3((unsigned)nb, (unsigned)L), dim3(256), 0, s, codes, ldc, n, K,
+                           sign, counts, S2, S3, err);
+        return hipGetLastError();
+    }
+    int64_t chunks = (n + B / 2 - 1) / (B / 2);
+    const int64_t want = (1024 + L - 1) / L;  // about 1024 blocks in total
+    if (chunks > want) chunks = want;
+    if (chunks < 1) chunks = 1;
+    int64_t rows = (n + chunks - 1) / chunks;
+    if (K == 16 && rows > 65535) {
+        rows = 65535;
+    }
+    chunks = (n + rows - 1) / rows;
+    const size_t lds = (size_t)(K == 16 ? (B >> 1) : B) * sizeof(uint32_t);
+    if (K == 16)
+        hipLaunchKernelGGL(update_lds_kernel<true>, dim3((unsigned)chunks, (unsigned)L), dim3(HIST_THREADS), lds, s,
+                           codes, ldc, n, rows, K, sign, counts, S2, S3, err);
+    else
+        hipLaunchKernelGGL(update_lds_kernel<false>, dim3((unsigned)chunks, (unsigned)L), dim3(HIST_THREADS), lds, s,
+                           codes, ldc, n, rows, K, sign, counts, S2, S3, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const int32_t* counts,
+                        float* s_out, uint32_t* T_out, u64* mom, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(score_kernel, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L, counts, s_out, T_out,
+                       mom);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode, double alpha,
+                            DevThresh* out, hipStream_t s) {
+    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(64), 0, s, n, L, S2, S3, mom, mode, alpha, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(flags_kernel, dim3((unsigned)nb), dim3(256), 0, s, T, n, (double)L * tau,
+                       mode == ACE_THR_CONST ? 1 : 0, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_sums(const int32_t* counts, int K, int L, u64* S2, u64* S3, hipStream_t s) {
+    hipLaunchKernelGGL(table_sums_kernel, dim3((unsigned)L), dim3(256), 0, s, counts, K, S2, S3);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t words = (int64_t)(bytes / 4);
+    int64_t nb = (words + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)nb), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+}  // namespace ace

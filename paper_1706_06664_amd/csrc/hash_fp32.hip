@@ -1,0 +1,229 @@
+// SRP hashing on FP32 MFMA (Sec. 2.1 signed random projections, Sec. 3.2 K-bit codes).
+//
+// One launch computes P = X W for a chunk of rows on v_mfma_f32_16x16x4f32 and never
+// writes P: the epilogue turns each 16-column output tile (one table) into bits
+// (p > 0), recomputes in FP64 every projection whose FP32 value lies inside its
+// error bound, and packs the 16 bits of each row into a uint16 code.
+//
+// Error bound of an FP32 projection (Higham, Accuracy and Stability of Numerical
+// Algorithms, 2nd ed., Sec. 3.1): every term x_t w_t of a sum of d products passes
+// through at most d+1 roundings of relative size u <= 2^-23 (this covers
+// round-to-nearest and truncation, in any summation order), so
+//   |p32 - p| <= gamma_h(u) sum_t |x_t w_t| <= gamma_h(u) ||x|| ||w||
+// with h = d+1.  The library uses h = 2d + 8 for headroom against accumulation
+// details of the matrix unit it does not rely on, plus an absolute term for
+// flushed subnormals.  Outside the bound the sign of p32 is the sign of p; inside
+// it the FP64 sum over ascending t is taken (products of FP32 values are exact in
+// FP64, so this is the same value a plain FP64 loop produces).
+//
+// Tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns).  A workgroup tile is
+// 128 rows x 2*TW tables (32*TW padded columns); each wave holds 64 rows x TW
+// tables = 4 x TW MFMA tiles of 16x16.  The contraction runs in chunks of 32 through
+// LDS; both operands are stored k-contiguous so each lane reads one float4 per
+// 16-wide k block and feeds four MFMAs with it.
+#include "ace_internal.h"
+
+namespace ace {
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int BK = 32;
+constexpr int LDSW = BK + 4;  // padded LDS row stride (floats)
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane) {
+    // Lane l wants row rho = l & 15 of a 16-row tile; that row's 16 bits sit in ballot
+    // r = rho & 3, bit field g = rho >> 2 (lane 16g + c holds column c of row 4g + r).
+    const int r = lane & 3, g = (lane & 15) >> 2;
+    u64 m = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
+    return (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int TW, bool VEC>
+__global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
+    constexpr int NB = 32 * TW;
+    __shared__ float As[BM * LDSW];
+    __shared__ float Bs[NB * LDSW];
+    __shared__ float rowb[BM];
+
+    // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).
+    // Give the blocks of one XCD all column tiles of the same row tile, back to back,
+    // so that XCD's L2 serves the repeated reads of the X tile.
+    const int64_t bid = blockIdx.x;
+    const int64_t xcd = bid & 7, local = bid >> 3;
+    const int64_t tile_n = local % a.n_tiles_n;
+    const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
+    if (tile_m >= a.n_tiles_m) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t row0 = tile_m * BM;
+    const int col0 = (int)tile_n * NB;
+
+    f4 acc[4][TW];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // A-tile role: thread -> row lr, 16 consecutive k at lk.
+    const int lr = tid >> 1, lk = (tid & 1) * 16;
+    const int64_t grow_ld = row0 + lr;
+    const bool row_ok = grow_ld < a.n;
+    const float* xrow = a.X + (row_ok ? grow_ld : 0) * (int64_t)a.d;
+    double ss = 0.0;
+
+    for (int k0 = 0; k0 < a.d; k0 += BK) {
+        float v[16];
+        if (VEC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + lk + 4 * q;
+                f4 t = f4{0.f, 0.f, 0.f, 0.f};
+                if (row_ok && k < a.d) t = *reinterpret_cast<const f4*>(xrow + k);
+                v[4 * q + 0] = t[0];
+                v[4 * q + 1] = t[1];
+                v[4 * q + 2] = t[2];
+                v[4 * q + 3] = t[3];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int k = k0 + lk + e;
+                v[e] = (row_ok && k < a.d) ? xrow[k] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) ss += (double)v[e] * (double)v[e];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<f4*>(As + lr * LDSW + lk + 4 * q) =
+                f4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+        // B tile: NB columns x 32 k as float4 quads; W is zero-padded to DP and NP.
+#pragma unroll
+        for (int s = 0; s < TW; ++s) {
+            const int q = tid + 256 * s;
+            const int col = q >> 3, kq = (q & 7) * 4;
+            const f4 t = *reinterpret_cast<const f4*>(a.Wt + (int64_t)(col0 + col) * a.DP + k0 + kq);
+            *reinterpret_cast<f4*>(Bs + col * LDSW + kq) = t;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < BK; kb += 16) {
+            // MFMA step s of this block uses k = kb + 4*(lane>>4) + s on both operands.
+            f4 af[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                af[b] = *reinterpret_cast<const f4*>(As + (wm * 64 + 16 * b + (lane & 15)) * LDSW + kb +
+                                                     4 * (lane >> 4));
+#pragma unroll
+            for (int t = 0; t < TW; ++t) {
+                const f4 bf = *reinterpret_cast<const f4*>(Bs + ((wn * TW + t) * 16 + (lane & 15)) * LDSW +
+                                                           kb + 4 * (lane >> 4));
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][0], bf[0], acc[b][t], 0, 0, 0);
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][1], bf[1], acc[b][t], 0, 0, 0);
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][2], bf[2], acc[b][t], 0, 0, 0);
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][3], bf[3], acc[b][t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Row bound factor: gx * ||x|| (FP64 sum of squares, rounded up by a relative 2^-20).
+    ss += __shfl_xor(ss, 1, 64);
+    if ((tid & 1) == 0) rowb[lr] = (float)(a.gx * sqrt(ss) * (1.0 + 0x1p-20));
+    __syncthreads();
+
+    const int kin = lane >> 4, cl = lane & 15;
+    const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
+    uint32_t n_ref = 0, n_flip = 0;
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const int table = (col0 >> 4) + wn * TW + t;
+        const int cp = col0 + (wn * TW + t) * 16 + cl;
+        const float wbv = a.wb[cp];
+        uint32_t code = 0, rcode = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            u64 mb[4], mr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lrow = wm * 64 + 16 * b + 4 * kin + r;
+                const int64_t grow = row0 + lrow;
+                const float p = acc[b][t][r];
+                bool bit = p > 0.f;
+                bool unc = false;
+                if (a.refine && wbv >= 0.f && grow < a.n) {
+                    const float thr = fmaf(rowb[lrow], wbv, a.eps_abs);
+                    unc = !(fabsf(p) > thr);  // NaN is refined too
+                }
+                if (__any(unc)) {
+                    if (unc) {
+                        const float* xr = a.X + grow * (int64_t)a.d;
+                        const float* wr = a.Wt + (int64_t)cp * a.DP;
+                        double s = 0.0;
+                        for (int u = 0; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
+                        const bool nb = s > 0.0;
+                        n_flip += (nb != bit) ? 1u : 0u;
+                        n_ref += 1u;
+                        bit = nb;
+                    }
+                }
+                mb[r] = __ballot(bit);
+                mr[r] = __ballot(unc);
+            }
+            if ((lane >> 4) == b) {
+                code = select_code(mb[0], mb[1], mb[2], mb[3], lane);
+                rcode = select_code(mr[0], mr[1], mr[2], mr[3], lane);
+            }
+        }
+        const int64_t orow = row0 + wm * 64 + lane;
+        if (table < a.L && orow < a.n) {
+            a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+            if (a.refined) a.refined[(int64_t)table * a.ldc + orow] = (uint16_t)(rcode & kmask);
+        }
+    }
+    if (__any(n_ref != 0)) {
+        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
+        if (lane == 0) {
+            atomicAdd(&a.counters[0], (u64)r);
+            if (f) atomicAdd(&a.counters[1], (u64)f);
+        }
+    }
+}
+
+template <int TW>
+hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
+    const int64_t groups = (a.n_tiles_m + 7) / 8;
+    const int64_t blocks = groups * 8 * a.n_tiles_n;
+    if (vec)
+        hipLaunchKernelGGL((hash_fp32_kernel<TW, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((hash_fp32_kernel<TW, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s) {
+    switch (TW) {
+        case 1: return launch_tw<1>(a, vec, s);
+        case 2: return launch_tw<2>(a, vec, s);
+        case 4: return launch_tw<4>(a, vec, s);
+        case 5: return launch_tw<5>(a, vec, s);
+        case 8: return launch_tw<8>(a, vec, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ace

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+symbol the header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "ace.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:ace_status|const char\*)\s+(ace_\w+)\s*\(", text, re.M)))
+
+
+def _lib():
+    from paper_1706_06664_amd import load_library
+    return load_library()
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1706_06664_amd import EXPORTS
+    assert sorted(EXPORTS) == names
+
+
+def test_status_strings_and_version():
+    lib = _lib()
+    assert lib.ace_status_string(0) == b"ACE_OK"
+    assert lib.ace_status_string(3) == b"ACE_E_OVERFLOW"
+    assert b"gfx950" in lib.ace_version()
+
+
+@pytest.mark.parametrize("field,value", [("d", 0), ("K", 0), ("K", 17), ("L", 0), ("L", 5000),
+                                         ("precision", 7), ("refine", 2), ("max_batch_rows", -1),
+                                         ("mem_budget", -5), ("device", -1)])
+def test_create_rejects_bad_config(field, value):
+    from paper_1706_06664_amd.ace import Config
+    lib = _lib()
+    cfg = Config(8, 6, 4, 0, 1, 0, 0, 0)
+    setattr(cfg, field, value)
+    W = np.zeros((8, 24), np.float32)
+    h = ctypes.c_void_p()
+    assert lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == 1
+    assert h.value is None
+
+
+def test_null_arguments_rejected():
+    lib = _lib()
+    from paper_1706_06664_amd.ace import Config
+    cfg = Config(8, 6, 4, 0, 1, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.ace_create(None, None, ctypes.byref(h)) == 1
+    assert lib.ace_create(ctypes.byref(cfg), None, ctypes.byref(h)) == 1
+    assert lib.ace_insert(None, None, 10, None) == 1
+    assert lib.ace_score(None, None, 10, None, None, None) == 1
+    assert lib.ace_destroy(None) == 0
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1706_06664_amd import ace as m
+    saved = m._lib
+    m._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            m.load_library(str(tmp_path / "missing.so"))
+    finally:
+        m._lib = saved

@@ -1,0 +1,220 @@
+"""HIP path vs the oracle, element by element, through the C ABI (needs the GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from ace_inputs import c1_points, c2_points, projection_matrix, gaussian_clusters
+from tests.parity import compare_codes, full_parity, recount
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1706_06664_amd import load_library
+    load_library()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_mfma_layout_small():
+    """One row tile, one table, FP32: tiny case checks operand and output lane layout."""
+    rng = np.random.default_rng(100)
+    X = rng.standard_normal((16, 4)).astype(np.float32)
+    W = rng.standard_normal((4, 16)).astype(np.float32)
+    r = full_parity(X, W, 16, 1)
+    _say(r)
+
+
+def test_parity_small_clusters():
+    """Clustered workload at 10,000 x 32, K=10, L=20, FP32 (all rows, all stats)."""
+    X, _ = c1_points()
+    W = projection_matrix(32, 10, 20, 1706066641)
+    r = full_parity(X, W, 10, 20)
+    _say(r)
+    assert r["differing_bits"] == 0
+
+
+@pytest.mark.parametrize("n,d,K,L", [
+    (1, 5, 1, 1), (127, 33, 15, 3), (129, 120, 15, 50), (300, 7, 16, 4), (1000, 64, 10, 64),
+    (777, 1, 4, 100), (2048, 32, 12, 9), (515, 130, 16, 13),
+])
+def test_parity_shapes(n, d, K, L):
+    X, _ = gaussian_clusters(n, d, 3, 0.05, seed=n + d)
+    W = projection_matrix(d, K, L, 7 + n)
+    r = full_parity(X, W, K, L)
+    _say((n, d, K, L, r))
+
+
+def test_parity_chunked_and_unaligned():
+    """max_batch_rows forces several chunks; an offset view makes rows unaligned (scalar loads)."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    X, _ = gaussian_clusters(2501, 36, 4, 0.02, seed=3)
+    W = projection_matrix(36, 15, 50, 11)
+    r = full_parity(X, W, 15, 50, max_batch_rows=1000)
+    _say(r)
+    big = torch.from_numpy(np.concatenate([np.zeros(1, np.float32), X.ravel()])).cuda()
+    Xoff = big[1:].view(2501, 36)
+    assert Xoff.data_ptr() % 16 != 0
+    ace = ACE(W, 15, 50, max_batch_rows=1000)
+    cg = codes_as_uint16(ace.hash(Xoff))
+    co, amb = oracle.hash_codes(X, W, 15, 50)
+    bad, _, _ = compare_codes(cg, co, amb)
+    assert bad == 0
+
+
+def test_zero_rows_identical_rows_near_orthogonal():
+    """Degenerate inputs: zero rows (every projection exactly 0, all refined, code 0);
+    identical rows (one hot bucket per table); rows orthogonal to chosen columns
+    before rounding (tiny projections decided by the FP64 tier)."""
+    rng = np.random.default_rng(5)
+    d, K, L = 24, 15, 8
+    W = projection_matrix(d, K, L, 99)
+    zero = np.zeros((200, d), np.float32)
+    same = np.repeat(rng.standard_normal((1, d)).astype(np.float32), 3000, axis=0)
+    near = []
+    for i in range(500):
+        y = rng.standard_normal(d)
+        c = rng.integers(0, K * L)
+        w = W[:, c].astype(np.float64)
+        near.append((y - (y @ w) / (w @ w) * w).astype(np.float32))
+    X = np.concatenate([zero, same, np.array(near)], axis=0)
+    r = full_parity(X, W, K, L)
+    _say(r)
+    assert r["bits_refined"] >= 200 * K * L
+
+
+def test_refine_off_respects_bound():
+    """Raw FP32 MFMA signs (refine off) may differ from the FP64 signs only where
+    |p64| is inside the library's stated FP32 bound gamma_{2d+8}(2^-23) ||x|| ||w||."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    rng = np.random.default_rng(8)
+    d, K, L = 120, 15, 50
+    X, _ = c2_points(n=4000, seed=8)
+    W = projection_matrix(d, K, L, 4)
+    near = []
+    for i in range(2000):
+        y = X[rng.integers(0, 4000)].astype(np.float64)
+        c = rng.integers(0, K * L)
+        w = W[:, c].astype(np.float64)
+        near.append((y - (y @ w) / (w @ w) * w).astype(np.float32))
+    X = np.concatenate([X, np.array(near)], axis=0)
+    ace = ACE(W, K, L, refine=False)
+    cg = codes_as_uint16(ace.hash(torch.from_numpy(X).cuda()))
+    P, _ = oracle.project(X, W)
+    u, h = 2.0 ** -23, 2 * d + 8
+    gam = h * u / (1 - h * u)
+    bound = gam * np.linalg.norm(X.astype(np.float64), axis=1)[:, None] * np.linalg.norm(W.astype(np.float64), axis=0)[None, :]
+    bits_ref = (P > 0)
+    n_viol = 0
+    n_flip = 0
+    worst = 0.0
+    for j in range(L):
+        for k in range(K):
+            c = j * K + k
+            gbit = ((cg[:, j] >> k) & 1).astype(bool)
+            diff = gbit != bits_ref[:, c]
+            n_flip += int(diff.sum())
+            if diff.any():
+                ratio = np.abs(P[diff, c]) / bound[diff, c]
+                worst = max(worst, float(ratio.max()))
+                n_viol += int((ratio > 1).sum())
+    _say({"raw_flips": n_flip, "worst_ratio": worst})
+    assert n_viol == 0
+
+
+def test_delete_matches_oracle():
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    X, _ = gaussian_clusters(6000, 20, 5, 0.01, seed=21)
+    K, L = 12, 16
+    W = projection_matrix(20, K, L, 21)
+    drop = np.random.default_rng(1).permutation(6000)[:2500]
+    ace = ACE(W, K, L)
+    Xd = torch.from_numpy(X).cuda()
+    ace.insert(Xd)
+    ace.delete(Xd[torch.from_numpy(drop).cuda()].contiguous())
+    co, amb = oracle.hash_codes(X, W, K, L)
+    sk = oracle.Sketch(K, L)
+    sk.insert_codes(co)
+    assert sk.delete_codes(co[drop]) == 0
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    S2, S3 = ace.table_stats()
+    assert np.array_equal(S2, sk.S2) and np.array_equal(S3, sk.S3)
+    th = ace.threshold("const", 1.0)
+    rc, tho = sk.threshold(oracle.MODE_CONST, 1.0)
+    assert th["n"] == 3500 and abs(th["mu"] - tho["mu"]) <= 1e-12 * tho["mu"]
+
+
+def test_codes_entry_points_and_checkpoint():
+    import torch
+    from paper_1706_06664_amd import ACE
+    X, _ = gaussian_clusters(4000, 16, 3, 0.01, seed=31)
+    K, L = 11, 10
+    W = projection_matrix(16, K, L, 31)
+    a = ACE(W, K, L)
+    Xd = torch.from_numpy(X).cuda()
+    codes = a.hash(Xd)
+    a.insert_codes(codes)
+    s1, T1 = a.score_codes(codes)
+    b = ACE(W, K, L)
+    b.set_counts(a.counts(), 4000)
+    s2, T2 = b.score(Xd)
+    assert torch.equal(T1, T2)
+    S2a, S3a = a.table_stats()
+    S2b, S3b = b.table_stats()
+    assert np.array_equal(S2a, S2b) and np.array_equal(S3a, S3b)
+
+
+def test_error_paths():
+    import torch
+    from paper_1706_06664_amd import ACE, AceError
+    W = projection_matrix(8, 6, 4, 1)
+    torch.manual_seed(0)
+    X = torch.randn(100, 8, device="cuda")
+    a = ACE(W, 6, 4)
+    with pytest.raises(AceError) as e:
+        a.threshold("scored")
+    assert e.value.status == 4                      # ACE_E_EMPTY
+    import paper_1706_06664_amd.ace as m
+    assert a.lib.ace_debug_set_capacity(a.h, 150) == 0
+    a.insert(X)
+    with pytest.raises(AceError) as e:
+        a.insert(X)
+    assert e.value.status == 3                      # ACE_E_OVERFLOW, nothing enqueued
+    assert a.counts().sum() == 100 * 4
+    assert a.lib.ace_debug_fail_next(a.h) == 0
+    with pytest.raises(AceError) as e:
+        a.score(X)
+    assert e.value.status == 5                      # ACE_E_DEVICE ...
+    with pytest.raises(AceError) as e:
+        a.threshold("const")
+    assert e.value.status == 5                      # ... and sticky
+    with pytest.raises(AceError) as e:
+        ACE(W, 6, 4, mem_budget=1000)
+    assert e.value.status == 2                      # ACE_E_NOMEM
+    b = ACE(W, 6, 4)
+    with pytest.raises(AceError) as e:
+        b.delete(X[:3].contiguous())
+    assert e.value.status == 6                      # ACE_E_STATE: more deletes than points
+    b.insert(X[:10].contiguous())
+    b.delete(X[50:53].contiguous())                 # never inserted: a bucket goes below zero
+    with pytest.raises(AceError) as e:
+        b.threshold("const")
+    assert e.value.status == 6
+
+
+@pytest.mark.timeout(600)
+def test_parity_connection_log_full():
+    """Full connection-log workload: 494,021 x 120, K=15, L=50, FP32."""
+    X, _ = c2_points()
+    W = projection_matrix(120, 15, 50, 1706066642)
+    r = full_parity(X, W, 15, 50)
+    _say(r)
