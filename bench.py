@@ -112,7 +112,7 @@ def main():
             "frac": achieved / PEAK["fp32"], "traffic": None,
             "kernel": "hash_fp32_kernel (projection + sign-pack + FP64 refine)",
             "avg_launch_ms": hash_avg_ms, "rows_per_launch": rows_per_launch}
-    phases = {k: prof[k] / args.steps for k in ("hash_ms", "update_ms", "score_ms", "other_ms")}
+    phases = {k: prof[k] / args.steps for k in ("hash_ms", "refine_ms", "update_ms", "score_ms", "other_ms")}
 
     base = None
     if not args.no_cpu_baseline:

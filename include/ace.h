@@ -188,6 +188,8 @@ typedef struct {
     int64_t score_launches;
     double other_ms;         /* threshold, flags, zeroing */
     int64_t other_launches;
+    double refine_ms;        /* FP64 pass over projections inside the low-precision bound */
+    int64_t refine_launches;
 } ace_profile;
 
 /* Turn event timing on (1) or off (0).  While on, each launch records two events on its
@@ -209,6 +211,9 @@ const char* ace_version(void);
  * reached with small inputs (0 restores the default). */
 ace_status ace_debug_fail_next(ace_ctx ctx);
 ace_status ace_debug_set_capacity(ace_ctx ctx, int64_t max_points);
+/* Lower the number of queued uncertain projections per chunk (0 restores the default), so
+ * that the in-kernel path taken when the queue is full can be exercised. */
+ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,8 @@ STATUS = {0: "ACE_OK", 1: "ACE_E_INVALID", 2: "ACE_E_NOMEM", 3: "ACE_E_OVERFLOW"
 EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_insert", "ace_delete", "ace_score",
            "ace_threshold", "ace_flag", "ace_hash", "ace_insert_codes", "ace_score_codes", "ace_get_counts",
            "ace_get_table_stats", "ace_get_counters", "ace_set_counts", "ace_status_string", "ace_version",
-           "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile"]
+           "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
+           "ace_debug_set_refine_queue"]
 
 
 class AceError(RuntimeError):
@@ -52,7 +53,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("hash_ms", ctypes.c_double), ("hash_launches", ctypes.c_int64), ("hash_rows", ctypes.c_int64),
                 ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64),
                 ("score_ms", ctypes.c_double), ("score_launches", ctypes.c_int64),
-                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64)]
+                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64),
+                ("refine_ms", ctypes.c_double), ("refine_launches", ctypes.c_int64)]
 
 
 class Counters(ctypes.Structure):
@@ -93,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "ace_debug_fail_next": [P],
         "ace_debug_set_capacity": [P, i64],
         "ace_profile_enable": [P, i32],
+        "ace_debug_set_refine_queue": [P, i64],
         "ace_get_profile": [P, ctypes.POINTER(Profile)],
     }
     for name, args in sigs.items():

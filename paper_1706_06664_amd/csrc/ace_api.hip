@@ -27,8 +27,12 @@ struct ace_ctx_s {
     u64* rcnt = nullptr;         // bits refined, bits flipped
     unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
     DevThresh* thr = nullptr;
-    uint16_t* ws_codes = nullptr;  // [L][ws_rows]
+    uint16_t* ws_codes = nullptr;  // [L][ws_rows] (+ padding for 32-bit patch atomics)
+    uint16_t* ws_refined = nullptr;  // same shape, allocated on first request
     int64_t ws_rows = 0;
+    u64* list = nullptr;           // queue of uncertain projections
+    u64* list_count = nullptr;
+    u64 list_alloc = 0, list_cap = 0;
 
     int64_t n_total = 0;
     int64_t cap = INT32_MAX;
@@ -69,7 +73,7 @@ ace_status dev_alloc(ace_ctx c, void** p, size_t bytes) {
     return ACE_OK;
 }
 
-enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3 };
+enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3, CLS_REFINE = 4 };
 
 hipEvent_t take_event(ace_ctx c) {
     if (!c->pool.empty()) {
@@ -115,7 +119,8 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes};
+    void* ptrs[] = {c->Wt, c->wb, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
+                    c->ws_refined, c->list, c->list_count};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -162,9 +167,15 @@ int pick_tw(int L) {
     return best;
 }
 
-// Hash rows [0, n) of X (one chunk of at most ws_rows rows) into codes[j*ldc + i].
-ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, uint16_t* codes, int64_t ldc, uint16_t* refined,
-                      hipStream_t s) {
+// Hash rows [0, n) of X (one chunk of at most ws_rows rows) into the workspace codes
+// [L][n]: projection + sign-pack, then the FP64 pass over the queued projections.
+ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, hipStream_t s) {
+    ace_status st = check(c, launch_zero(c->list_count, sizeof(u64), s));
+    if (st) return st;
+    if (want_refined) {
+        st = check(c, launch_zero(c->ws_refined, sizeof(uint16_t) * ((size_t)c->cfg.L * n + 2), s));
+        if (st) return st;
+    }
     HashArgs a;
     a.X = X;
     a.n = n;
@@ -179,20 +190,41 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, uint16_t* codes, int
     a.gx = c->gx;
     a.eps_abs = c->eps_abs;
     a.refine = c->cfg.refine;
-    a.codes = codes;
-    a.ldc = ldc;
-    a.refined = refined;
+    a.codes = c->ws_codes;
+    a.ldc = n;
+    a.list = c->list;
+    a.list_count = c->list_count;
+    a.list_cap = c->list_cap;
     a.counters = c->rcnt;
     const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
     c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
-    Bracket br(c, s, CLS_HASH, n);
-    return check(c, launch_hash_fp32(a, c->TW, vec, s));
+    {
+        Bracket br(c, s, CLS_HASH, n);
+        st = check(c, launch_hash_fp32(a, c->TW, vec, s));
+    }
+    if (st || !c->cfg.refine) return st;
+    RefineArgs r;
+    r.X = X;
+    r.d = c->cfg.d;
+    r.Wt = c->Wt;
+    r.DP = c->DP;
+    r.L = c->cfg.L;
+    r.K = c->cfg.K;
+    r.codes = c->ws_codes;
+    r.ldc = n;
+    r.refined = want_refined ? c->ws_refined : nullptr;
+    r.list = c->list;
+    r.list_count = c->list_count;
+    r.list_cap = c->list_cap;
+    r.counters = c->rcnt;
+    Bracket br(c, s, CLS_REFINE, n);
+    return check(c, launch_refine(r, (int64_t)c->list_cap, s));
 }
 
 ace_status update_rows(ace_ctx c, const float* X, int64_t n, int sign, hipStream_t s) {
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        ace_status st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, c->ws_codes, m, nullptr, s);
+        ace_status st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, false, s);
         if (st != ACE_OK) return st;
         {
             Bracket br(c, s, CLS_UPDATE, m);
@@ -273,7 +305,14 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 2);
     st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
-    st = st ? st : dev_alloc(c, (void**)&c->ws_codes, sizeof(uint16_t) * (size_t)L * c->ws_rows);
+    st = st ? st : dev_alloc(c, (void**)&c->ws_codes, sizeof(uint16_t) * ((size_t)L * c->ws_rows + 2));
+    // Queue for projections inside the FP32 bound: 1/32 of a chunk's bits (a full queue
+    // only slows the epilogue down, it never changes a result).
+    c->list_alloc = (u64)c->ws_rows * (u64)L * KPAD / 32;
+    if (c->list_alloc < 65536) c->list_alloc = 65536;
+    c->list_cap = c->list_alloc;
+    st = st ? st : dev_alloc(c, (void**)&c->list, sizeof(u64) * (size_t)c->list_alloc);
+    st = st ? st : dev_alloc(c, (void**)&c->list_count, sizeof(u64));
     if (st != ACE_OK) {
         free_all(c);
         delete c;
@@ -402,7 +441,7 @@ ace_status ace_score(ace_ctx c, const float* X, int64_t n, float* s_out, uint32_
     hipStream_t s = (hipStream_t)stream;
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, c->ws_codes, m, nullptr, s);
+        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, false, s);
         if (st) return st;
         {
             Bracket br(c, s, CLS_SCORE, m);
@@ -432,12 +471,24 @@ ace_status ace_hash(ace_ctx c, const float* X, int64_t n, uint16_t* codes, uint1
     if (st) return st;
     if (n < 0 || (n > 0 && (!X || !codes))) return ACE_E_INVALID;
     if (n == 0) return ACE_OK;
-    if (take_injected_failure(c)) return ACE_E_DEVICE;
     DeviceGuard g(c->cfg.device);
+    if (refined && !c->ws_refined) {
+        st = dev_alloc(c, (void**)&c->ws_refined, sizeof(uint16_t) * ((size_t)c->cfg.L * c->ws_rows + 2));
+        if (st) return st;
+    }
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
+    const size_t L = (size_t)c->cfg.L;
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, codes + r0, n, refined ? refined + r0 : nullptr, s);
+        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, refined != nullptr, s);
+        if (st) return st;
+        // Workspace [L][m] -> caller's [L][n] at column r0.
+        st = check(c, hipMemcpy2DAsync(codes + r0, sizeof(uint16_t) * n, c->ws_codes, sizeof(uint16_t) * m,
+                                       sizeof(uint16_t) * m, L, hipMemcpyDeviceToDevice, s));
+        if (!st && refined)
+            st = check(c, hipMemcpy2DAsync(refined + r0, sizeof(uint16_t) * n, c->ws_refined, sizeof(uint16_t) * m,
+                                           sizeof(uint16_t) * m, L, hipMemcpyDeviceToDevice, s));
         if (st) return st;
     }
     return ACE_OK;
@@ -588,6 +639,7 @@ ace_status ace_get_profile(ace_ctx c, ace_profile* out) {
             case CLS_HASH: out->hash_ms += ms; out->hash_launches++; out->hash_rows += t.rows; break;
             case CLS_UPDATE: out->update_ms += ms; out->update_launches++; break;
             case CLS_SCORE: out->score_ms += ms; out->score_launches++; break;
+            case CLS_REFINE: out->refine_ms += ms; out->refine_launches++; break;
             default: out->other_ms += ms; out->other_launches++; break;
         }
         c->pool.push_back(t.a);
@@ -600,6 +652,12 @@ ace_status ace_get_profile(ace_ctx c, ace_profile* out) {
 ace_status ace_debug_fail_next(ace_ctx c) {
     if (!c) return ACE_E_INVALID;
     c->fail_next = 1;
+    return ACE_OK;
+}
+
+ace_status ace_debug_set_refine_queue(ace_ctx c, int64_t entries) {
+    if (!c || entries < 0) return ACE_E_INVALID;
+    c->list_cap = (entries == 0 || (u64)entries > c->list_alloc) ? c->list_alloc : (u64)entries;
     return ACE_OK;
 }
 

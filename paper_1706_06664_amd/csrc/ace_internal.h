@@ -35,7 +35,25 @@ struct HashArgs {
     int32_t refine;
     uint16_t* codes;       // [L][ldc]: code of row i of this chunk in table j at j*ldc + i
     int64_t ldc;
-    uint16_t* refined;     // same layout or null: mask of bits recomputed in FP64
+    u64* list;             // queue of uncertain projections: row | column << 32 | raw bit << 63
+    u64* list_count;       // entries appended (may exceed list_cap)
+    u64 list_cap;
+    u64* counters;         // [0] bits refined, [1] refined bits that flipped (queue-full path)
+};
+
+// Arguments of the FP64 pass over the queued projections.
+struct RefineArgs {
+    const float* X;
+    int32_t d;
+    const float* Wt;
+    int32_t DP;
+    int32_t L, K;
+    uint16_t* codes;       // [L][ldc], patched in place
+    int64_t ldc;
+    uint16_t* refined;     // same layout or null: refined bits are set
+    const u64* list;
+    const u64* list_count;
+    u64 list_cap;
     u64* counters;         // [0] bits refined, [1] refined bits that flipped
 };
 
@@ -48,6 +66,7 @@ struct DevThresh {
 
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
+hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, hipStream_t s);
 // sign = +1 insert, -1 delete
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
                                int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s);

@@ -2,8 +2,10 @@
 //
 // One launch computes P = X W for a chunk of rows on v_mfma_f32_16x16x4f32 and never
 // writes P: the epilogue turns each 16-column output tile (one table) into bits
-// (p > 0), recomputes in FP64 every projection whose FP32 value lies inside its
-// error bound, and packs the 16 bits of each row into a uint16 code.
+// (p > 0) and packs the 16 bits of each row into a uint16 code.  Every projection
+// whose FP32 value lies inside its error bound is queued (one atomic per wave) and
+// decided by refine_kernel in FP64; if the queue is full the epilogue decides it
+// in place.
 //
 // Error bound of an FP32 projection (Higham, Accuracy and Stability of Numerical
 // Algorithms, 2nd ed., Sec. 3.1): every term x_t w_t of a sum of d products passes
@@ -80,6 +82,11 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
     const float* xrow = a.X + (row_ok ? grow_ld : 0) * (int64_t)a.d;
     double ss = 0.0;
 
+    // Column bound factors of this wave's tables (read early; used in the epilogue).
+    float wcol[TW];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) wcol[t] = a.wb[col0 + (wn * TW + t) * 16 + (lane & 15)];
+
     for (int k0 = 0; k0 < a.d; k0 += BK) {
         float v[16];
         if (VEC) {
@@ -144,54 +151,77 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
     if ((tid & 1) == 0) rowb[lr] = (float)(a.gx * sqrt(ss) * (1.0 + 0x1p-20));
     __syncthreads();
 
+    // This lane's 16 accumulator rows: wm*64 + 16b + 4*kin + r (b, r = 0..3), index e = 4b + r.
     const int kin = lane >> 4, cl = lane & 15;
+    float rbnd[16];
+    uint32_t rok = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const f4 v = *reinterpret_cast<const f4*>(rowb + wm * 64 + 16 * b + 4 * kin);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            rbnd[4 * b + r] = v[r];
+            rok |= (row0 + wm * 64 + 16 * b + 4 * kin + r < a.n) ? (1u << (4 * b + r)) : 0u;
+        }
+    }
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
-    uint32_t n_ref = 0, n_flip = 0;
+    const int64_t orow = row0 + wm * 64 + lane;  // the row whose codes this lane stores
+    uint32_t n_ref = 0, n_flip = 0;                // projections decided in place (queue full)
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         const int table = (col0 >> 4) + wn * TW + t;
         const int cp = col0 + (wn * TW + t) * 16 + cl;
-        const float wbv = a.wb[cp];
-        uint32_t code = 0, rcode = 0;
+        const float wbv = wcol[t];
+        uint32_t umask = 0;
+        if (a.refine && wbv >= 0.f) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
+                umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;  // NaN is uncertain too
+            }
+            umask &= rok;
+        }
+        if (__any(umask != 0)) {
+            // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave.
+            const uint32_t mine = __popc(umask);
+            uint32_t incl = mine;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            u64 base = 0;
+            if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
+            base = __shfl(base, 0, 64);
+            u64 slot = base + (incl - mine);
+            for (int e = 0; e < 16; ++e) {
+                if (!((umask >> e) & 1u)) continue;
+                const int64_t grow = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
+                const float p = acc[e >> 2][t][e & 3];
+                if (slot < a.list_cap) {
+                    a.list[slot] = (u64)(uint32_t)grow | ((u64)cp << 32) | ((p > 0.f) ? (1ull << 63) : 0ull);
+                } else {
+                    // Queue full: decide here (same FP64 sum as the FP64 pass).
+                    const float* xr = a.X + grow * (int64_t)a.d;
+                    const float* wr = a.Wt + (int64_t)cp * a.DP;
+                    double sacc = 0.0;
+                    for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
+                    n_ref += 1u;
+                    n_flip += ((sacc > 0.0) != (p > 0.f)) ? 1u : 0u;
+                    acc[e >> 2][t][e & 3] = sacc > 0.0 ? 1.f : -1.f;
+                }
+                ++slot;
+            }
+        }
+        uint32_t code = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            u64 mb[4], mr[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int lrow = wm * 64 + 16 * b + 4 * kin + r;
-                const int64_t grow = row0 + lrow;
-                const float p = acc[b][t][r];
-                bool bit = p > 0.f;
-                bool unc = false;
-                if (a.refine && wbv >= 0.f && grow < a.n) {
-                    const float thr = fmaf(rowb[lrow], wbv, a.eps_abs);
-                    unc = !(fabsf(p) > thr);  // NaN is refined too
-                }
-                if (__any(unc)) {
-                    if (unc) {
-                        const float* xr = a.X + grow * (int64_t)a.d;
-                        const float* wr = a.Wt + (int64_t)cp * a.DP;
-                        double s = 0.0;
-                        for (int u = 0; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
-                        const bool nb = s > 0.0;
-                        n_flip += (nb != bit) ? 1u : 0u;
-                        n_ref += 1u;
-                        bit = nb;
-                    }
-                }
-                mb[r] = __ballot(bit);
-                mr[r] = __ballot(unc);
-            }
-            if ((lane >> 4) == b) {
-                code = select_code(mb[0], mb[1], mb[2], mb[3], lane);
-                rcode = select_code(mr[0], mr[1], mr[2], mr[3], lane);
-            }
+            const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
+                                            __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
+            code = (kin == b) ? cb : code;
         }
-        const int64_t orow = row0 + wm * 64 + lane;
-        if (table < a.L && orow < a.n) {
-            a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
-            if (a.refined) a.refined[(int64_t)table * a.ldc + orow] = (uint16_t)(rcode & kmask);
-        }
+        if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
     if (__any(n_ref != 0)) {
         const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
@@ -199,6 +229,48 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
             atomicAdd(&a.counters[0], (u64)r);
             if (f) atomicAdd(&a.counters[1], (u64)f);
         }
+    }
+}
+
+// FP64 pass over the queued projections.  Entry = row | column << 32 | raw bit << 63.
+// The FP64 sum runs over ascending t from the FP32 inputs; the code bit is set or
+// cleared with a 32-bit atomic on the word holding the code (the workspace is padded
+// so that word never leaves it).  refined (optional, same layout) gets the bit marked.
+__global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
+    const u64 n_ent = min(*a.list_count, a.list_cap);
+    uint32_t n_ref = 0, n_flip = 0;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_ent; i += (u64)gridDim.x * blockDim.x) {
+        const u64 e = a.list[i];
+        const int64_t row = (int64_t)(e & 0xFFFFFFFFull);
+        const int cp = (int)((e >> 32) & 0xFFFFu);
+        const bool raw = (e >> 63) != 0;
+        const float* xr = a.X + row * (int64_t)a.d;
+        const float* wr = a.Wt + (int64_t)cp * a.DP;
+        double s = 0.0;
+        for (int u = 0; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
+        const bool bit = s > 0.0;
+        const int table = cp >> 4, k = cp & 15;
+        if (table < a.L && k < a.K) {
+            const size_t idx = (size_t)table * a.ldc + row;
+            const uintptr_t addr = reinterpret_cast<uintptr_t>(a.codes + idx);
+            uint32_t* word = reinterpret_cast<uint32_t*>(addr & ~(uintptr_t)3);
+            const uint32_t m = 1u << (k + ((addr & 2) ? 16 : 0));
+            if (bit != raw) {
+                if (bit) atomicOr(word, m);
+                else atomicAnd(word, ~m);
+            }
+            if (a.refined) {
+                const uintptr_t ra = reinterpret_cast<uintptr_t>(a.refined + idx);
+                atomicOr(reinterpret_cast<uint32_t*>(ra & ~(uintptr_t)3), 1u << (k + ((ra & 2) ? 16 : 0)));
+            }
+            n_ref += 1u;
+            n_flip += (bit != raw) ? 1u : 0u;
+        }
+    }
+    const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
+    if ((threadIdx.x & 63) == 0 && r) {
+        atomicAdd(&a.counters[0], (u64)r);
+        if (f) atomicAdd(&a.counters[1], (u64)f);
     }
 }
 
@@ -214,6 +286,14 @@ hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, hipStream_t s) {
+    int64_t blocks = (max_entries + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(refine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s) {
     switch (TW) {

@@ -218,3 +218,37 @@ def test_parity_connection_log_full():
     W = projection_matrix(120, 15, 50, 1706066642)
     r = full_parity(X, W, 15, 50)
     _say(r)
+
+
+def test_refine_queue_full_path():
+    """With the queue cut to 10 entries nearly every uncertain projection is decided inside
+    the projection kernel; codes and refine counts must match the default path."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    rng = np.random.default_rng(6)
+    d, K, L = 40, 16, 6
+    W = projection_matrix(d, K, L, 98)
+    zero = np.zeros((64, d), np.float32)
+    near = []
+    for i in range(700):
+        y = rng.standard_normal(d)
+        c = rng.integers(0, K * L)
+        w = W[:, c].astype(np.float64)
+        near.append((y - (y @ w) / (w @ w) * w).astype(np.float32))
+    X = np.concatenate([zero, np.array(near), rng.standard_normal((300, d)).astype(np.float32)], axis=0)
+    Xd = torch.from_numpy(X).cuda()
+    co, amb = oracle.hash_codes(X, W, K, L)
+    res = []
+    for q in (0, 10):
+        ace = ACE(W, K, L)
+        assert ace.lib.ace_debug_set_refine_queue(ace.h, q) == 0
+        cg, ref = ace.hash(Xd, want_refined=True)
+        cg = codes_as_uint16(cg)
+        bad, _, _ = compare_codes(cg, co, amb)
+        assert bad == 0
+        res.append((cg, ace.counters()["bits_refined"]))
+        if q == 0:
+            refm = codes_as_uint16(ref)
+            assert np.all(refm[:64] == (1 << K) - 1)      # zero rows: every bit refined
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1] and res[0][1] >= 64 * K * L
