@@ -20,6 +20,9 @@ struct ace_ctx_s {
 
     float* Wt = nullptr;   // [NP][DP]
     float* wb = nullptr;   // [NP]
+    uint16_t* Wh = nullptr;  // [NP][DP] split-BF16 hi / lo (BF16 precision)
+    uint16_t* Wl = nullptr;
+    float* wbA = nullptr;    // [4][NP] BF16 bound factors (A, B, C, absolute)
     int32_t* counts = nullptr;   // [L][2^K]
     u64* S2 = nullptr;           // [L]
     u64* S3 = nullptr;           // [L][2]
@@ -119,7 +122,7 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
+    void* ptrs[] = {c->Wt, c->wb, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
                     c->ws_refined, c->list, c->list_count};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -151,12 +154,27 @@ bool take_injected_failure(ace_ctx c) {
     return false;
 }
 
-int pick_tw(int L) {
+// Round-to-nearest-even FP32 -> BF16 (finite inputs), the same rounding the kernels use.
+uint16_t host_bf16_bits(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float host_bf16_val(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+}
+
+int pick_tw(int L, bool allow8) {
     // Fewest padded tables; ties go to the wider tile.
     const int cand[] = {5, 4, 8, 2, 1};
     int best = 5;
     long best_pad = -1;
     for (int tw : cand) {
+        if (tw == 8 && !allow8) continue;
         const long tiles = (L + 2 * tw - 1) / (2 * tw);
         const long pad = tiles * 2 * tw - L;
         if (best_pad < 0 || pad < best_pad) {
@@ -196,11 +214,21 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     a.list_count = c->list_count;
     a.list_cap = c->list_cap;
     a.counters = c->rcnt;
+    a.Wh = c->Wh;
+    a.Wl = c->Wl;
+    a.wbA = c->wbA;
+    a.wbB = c->wbA ? c->wbA + c->NP : nullptr;
+    a.wbC = c->wbA ? c->wbA + 2 * c->NP : nullptr;
+    a.wbE = c->wbA ? c->wbA + 3 * c->NP : nullptr;
+    a.norm_up = (float)(1.0 + ldexp((double)c->DP + 2.0, -23));
     const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
     c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
     {
         Bracket br(c, s, CLS_HASH, n);
-        st = check(c, launch_hash_fp32(a, c->TW, vec, s));
+        if (c->cfg.precision == ACE_BF16)
+            st = check(c, launch_hash_bf16(a, c->TW, vec, s));
+        else
+            st = check(c, launch_hash_fp32(a, c->TW, vec, s));
     }
     if (st || !c->cfg.refine) return st;
     RefineArgs r;
@@ -258,7 +286,7 @@ const char* ace_version(void) { return "ace-mi355x 0.1 (gfx950)"; }
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) {
     if (!cfg || !W_host || !out) return ACE_E_INVALID;
     if (cfg->d < 1 || cfg->K < 1 || cfg->K > 16 || cfg->L < 1 || cfg->L > 4096) return ACE_E_INVALID;
-    if (cfg->precision != ACE_FP32) return ACE_E_INVALID;
+    if (cfg->precision != ACE_FP32 && cfg->precision != ACE_BF16) return ACE_E_INVALID;
     if (cfg->refine != 0 && cfg->refine != 1) return ACE_E_INVALID;
     if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
     if ((int64_t)cfg->d > (int64_t)1 << 24) return ACE_E_INVALID;
@@ -284,7 +312,7 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     c->cfg = *cfg;
     if (c->cfg.max_batch_rows == 0) c->cfg.max_batch_rows = (int64_t)1 << 20;
     const int d = cfg->d, K = cfg->K, L = cfg->L;
-    c->TW = pick_tw(L);
+    c->TW = pick_tw(L, cfg->precision == ACE_FP32);
     c->n_tiles_n = (L + 2 * c->TW - 1) / (2 * c->TW);
     c->NP = c->n_tiles_n * 32 * c->TW;
     c->DP = (d + DPAD - 1) / DPAD * DPAD;
@@ -298,6 +326,11 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     ace_status st = ACE_OK;
     st = st ? st : dev_alloc(c, (void**)&c->Wt, sizeof(float) * (size_t)c->NP * c->DP);
     st = st ? st : dev_alloc(c, (void**)&c->wb, sizeof(float) * (size_t)c->NP);
+    if (cfg->precision == ACE_BF16) {
+        st = st ? st : dev_alloc(c, (void**)&c->Wh, sizeof(uint16_t) * (size_t)c->NP * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->Wl, sizeof(uint16_t) * (size_t)c->NP * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
+    }
     st = st ? st : dev_alloc(c, (void**)&c->counts, sizeof(int32_t) * (size_t)L * B);
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
@@ -332,7 +365,47 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
             }
             wb[cp] = (float)(sqrt(ss) * (1.0 + ldexp(1.0, -20)));
         }
-    hipError_t e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (cfg->precision == ACE_BF16) {
+        // Exact split w = w_h + w_l + rho_w and the column factors of the error bound
+        // (see the BF16 kernel): I = DP/32 MFMA instructions per chain, u = 2^-23.
+        std::vector<uint16_t> Wh((size_t)c->NP * c->DP, 0), Wl((size_t)c->NP * c->DP, 0);
+        std::vector<float> f((size_t)4 * c->NP, 0.f);
+        for (int cp = 0; cp < c->NP; ++cp) f[cp] = -1.f;
+        const double uu = ldexp(1.0, -23), I = (double)c->DP / 32.0, up = 1.0 + ldexp(1.0, -10);
+        for (int j = 0; j < L; ++j)
+            for (int k = 0; k < K; ++k) {
+                const int cp = j * KPAD + k;
+                double nh = 0, nl = 0, nr = 0, nw = 0;
+                for (int t = 0; t < d; ++t) {
+                    const float w = W_host[(size_t)t * K * L + (size_t)j * K + k];
+                    const uint16_t hb = host_bf16_bits(w);
+                    const float hv = host_bf16_val(hb);
+                    const float r1 = w - hv;
+                    const uint16_t lb = host_bf16_bits(r1);
+                    const float lv = host_bf16_val(lb);
+                    const float r2 = r1 - lv;
+                    Wh[(size_t)cp * c->DP + t] = hb;
+                    Wl[(size_t)cp * c->DP + t] = lb;
+                    nh += (double)hv * hv;
+                    nl += (double)lv * lv;
+                    nr += (double)r2 * r2;
+                    nw += (double)w * w;
+                }
+                nh = sqrt(nh);
+                nl = sqrt(nl);
+                nr = sqrt(nr);
+                nw = sqrt(nw);
+                f[cp] = (float)((nr + 34.0 * I * uu * nh + 68.0 * I * uu * nl + 2.0 * uu * (nh + nl)) * up);
+                f[c->NP + cp] = (float)((nl + nr + 68.0 * I * uu * nh + 2.0 * uu * nh) * up);
+                f[2 * c->NP + cp] = (float)(nw * up);
+                f[3 * c->NP + cp] = (float)(3.0 * ldexp(1.0, -126) * sqrt((double)c->DP) * (nw + 1.0) * up);
+            }
+        e = hipMemcpy(c->Wh, Wh.data(), Wh.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->Wl, Wl.data(), Wl.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->wbA, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->wb, wb.data(), wb.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->counts, 0, sizeof(int32_t) * (size_t)L * B);
     if (e == hipSuccess) e = hipMemset(c->S2, 0, sizeof(u64) * (size_t)L);

@@ -39,6 +39,14 @@ struct HashArgs {
     u64* list_count;       // entries appended (may exceed list_cap)
     u64 list_cap;
     u64* counters;         // [0] bits refined, [1] refined bits that flipped (queue-full path)
+    // Split-BF16 operands and bound factors (BF16 kernel only)
+    const uint16_t* Wh;    // [NP][DP] bf16 bits of w_h
+    const uint16_t* Wl;    // [NP][DP] bf16 bits of w_l
+    const float* wbA;      // [NP] column factors of ||x_h||, ||x_l||, ||rho_x|| and the absolute term;
+    const float* wbB;      //      wbA < 0 marks a pad column
+    const float* wbC;
+    const float* wbE;
+    float norm_up;         // rounding-up factor of FP32 sums of squares over d terms
 };
 
 // Arguments of the FP64 pass over the queued projections.
@@ -66,6 +74,7 @@ struct DevThresh {
 
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
+hipError_t launch_hash_bf16(const HashArgs& a, int TW, bool vec, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, hipStream_t s);
 // sign = +1 insert, -1 delete
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
