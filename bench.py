@@ -6,11 +6,14 @@ score every point (hash + gather-sum), compute the mean/std threshold and flag
 the points below it: the whole of Alg. 1 plus the Sec. 5.3 threshold over one
 synthetic batch that is already resident in HBM.
 
-Workload: connection-log shaped points, 494,021 x 120 (38 lognormal columns,
-82 one-hot columns, 20% anomalies from rare clusters), K = 15 bits, L = 50
-tables, FP32 projections refined in FP64 inside the FP32 error bound.
+Headline workload (the `value`): connection-log shaped points, 494,021 x 120
+(38 lognormal columns, 82 one-hot columns, 20% anomalies from rare clusters),
+K = 15 bits, L = 50 tables, FP32 projections refined in FP64 inside the FP32
+error bound.  Further fields: the same workload in split-BF16 mode, and a dense
+4,000,000 x 1024 low-rank workload (K = 15, L = 64) in FP32 and split-BF16 mode
+with refined fractions, raw flip rates and raw score errors.
 
-Prints one JSON line (see the keys below).
+Prints one JSON line.
 """
 import argparse
 import json
@@ -22,12 +25,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
+KERNEL = {"fp32": "hash_fp32_kernel", "bf16": "hash_bf16_kernel"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(X, W, K, L, target_s=12.0):
     """The oracle, untuned, on a bounded prefix of the workload: hash + insert every sample
-    row, then hash + score every sample row.  Returns points/s of that sample."""
-    import numpy as np
+    row, then hash + score + threshold + flags.  Returns points/s of that sample."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
@@ -47,36 +54,18 @@ def cpu_baseline(X, W, K, L, target_s=12.0):
     m2 = int(min(X.shape[0], max(m, m * target_s / max(t, 1e-3))))
     t2 = run(m2)
     return {"value": m2 / t2, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {m2} of {X.shape[0]} rows, hash+insert then hash+score+threshold, "
-                      f"{t2:.1f} s on {threads} OpenMP threads"}
+            "sample": f"first {m2} of {X.shape[0]} rows of the headline workload, hash+insert then "
+                      f"hash+score+threshold+flags, {t2:.1f} s on {threads} OpenMP threads"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout "
-              f"is a design, not a run)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run_workload(Xd, W, K, L, precision, steps, warmup):
+    """Time `steps` full steps; return timing, per-kernel event timing and counters."""
     import torch
-    from ace_inputs import c2_points, projection_matrix
     from paper_1706_06664_amd import ACE
-
-    K, L, d = 15, 50, 120
-    X, _ = c2_points()
-    n = X.shape[0]
-    W = projection_matrix(d, K, L, 1706066642)
-    dev = torch.device("cuda", 0)
-    Xd = torch.from_numpy(X).to(dev)
-    s = torch.empty(n, dtype=torch.float32, device=dev)
-    T = torch.empty(n, dtype=torch.int32, device=dev)
-    ace = ACE(W, K, L, precision="fp32", device=0)
+    n, d = Xd.shape
+    s = torch.empty(n, dtype=torch.float32, device=Xd.device)
+    T = torch.empty(n, dtype=torch.int32, device=Xd.device)
+    ace = ACE(W, K, L, precision=precision, device=0)
 
     def step():
         ace.reset()
@@ -85,48 +74,125 @@ def main():
         th = ace.threshold("scored", 1.0)
         return ace.flag(T, th["tau"], "scored"), th
 
-    print(f"[bench] warmup {args.warmup} steps, n={n}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ace.profile()  # discard
+    ace.profile()
+    c0 = ace.counters()
     ace.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         flags, th = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ace.profile_enable(False)
     prof = ace.profile()
-    cnt = ace.counters()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_per_step / 1e3)
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    c1 = ace.counters()
+    ace.close()
+    ms = (t1 - t0) * 1e3 / steps
+    hash_ms = prof["hash_ms"] / max(1, prof["hash_launches"])
+    rows = prof["hash_rows"] / max(1, prof["hash_launches"])
+    flop = 2.0 * rows * d * K * L
+    executed = flop * (16.0 / K) * (3.0 if precision == "bf16" else 1.0)
+    ach = flop / (hash_ms / 1e3)
+    bits = c1["bits_hashed"] - c0["bits_hashed"]
+    return {
+        "points_per_s": n / (ms / 1e3), "ms_per_step": ms,
+        "phase_ms_per_step": {k: prof[k] / steps for k in ("hash_ms", "refine_ms", "update_ms", "score_ms",
+                                                            "other_ms")},
+        "roofline": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[precision] / 1e12, "unit": "TFLOP/s",
+                     "frac": ach / PEAK[precision], "traffic": None, "kernel": KERNEL[precision],
+                     "avg_launch_ms": hash_ms, "rows_per_launch": rows,
+                     "executed_frac": executed / (hash_ms / 1e3) / PEAK[precision]},
+        "refined_bit_frac": (c1["bits_refined"] - c0["bits_refined"]) / max(1, bits),
+        "raw_flip_rate": (c1["bits_flipped"] - c0["bits_flipped"]) / max(1, bits),
+        "flagged": int(flags.sum().item()), "tau": th["tau"],
+    }
 
-    hash_avg_ms = prof["hash_ms"] / max(1, prof["hash_launches"])
-    rows_per_launch = prof["hash_rows"] / max(1, prof["hash_launches"])
-    flop_per_launch = 2.0 * rows_per_launch * d * K * L
-    achieved = flop_per_launch / (hash_avg_ms / 1e3)
-    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK["fp32"], "traffic": None,
-            "kernel": "hash_fp32_kernel (projection + sign-pack + FP64 refine)",
-            "avg_launch_ms": hash_avg_ms, "rows_per_launch": rows_per_launch}
-    phases = {k: prof[k] / args.steps for k in ("hash_ms", "refine_ms", "update_ms", "score_ms", "other_ms")}
+
+def raw_score_error(Xs, W, K, L, precision):
+    """Score error of raw low-precision signs (refinement off) against the refined scores,
+    which equal the FP64 oracle's (checked by the GPU tests): insert and score the sample."""
+    import numpy as np
+    import torch
+    from paper_1706_06664_amd import ACE
+    out = []
+    for refine in (True, False):
+        a = ACE(W, K, L, precision=precision, refine=refine)
+        a.insert(Xs)
+        s, T = a.score(Xs)
+        out.append(T.cpu().numpy().astype(np.float64))
+        a.close()
+    ref, raw = out
+    rel = np.abs(raw - ref) / np.maximum(ref, 1.0)
+    return {"rows": int(Xs.shape[0]), "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
+            "rows_changed": int((raw != ref).sum())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="skip the BF16 and 1024-d runs")
+    ap.add_argument("--low-rank-n", type=int, default=4_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout "
+              f"is a design, not a run)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from ace_inputs import c2_points, low_rank_points_torch, projection_matrix
+
+    K, L, d = 15, 50, 120
+    X, _ = c2_points()
+    n = X.shape[0]
+    W = projection_matrix(d, K, L, 1706066642)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    log(f"connection-log {n}x{d} fp32: warmup {args.warmup}, steps {args.steps}")
+    head = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup)
+    log(f"  {head['ms_per_step']:.3f} ms/step")
+
+    extra = {}
+    if not args.headline_only:
+        log("connection-log bf16")
+        b = run_workload(Xd, W, K, L, "bf16", args.steps, args.warmup)
+        extra["connection_log_bf16"] = b
+        extra["connection_log_bf16_speedup"] = head["ms_per_step"] / b["ms_per_step"]
+        log(f"  {b['ms_per_step']:.3f} ms/step")
+        del Xd
+        torch.cuda.empty_cache()
+        n3, d3, K3, L3 = args.low_rank_n, 1024, 15, 64
+        X3, _ = low_rank_points_torch(n3, d3, seed=3, device="cuda:0")
+        W3 = projection_matrix(d3, K3, L3, 1706066643)
+        lr = {"workload": f"low-rank {n3}x{d3}, K={K3}, L={L3}"}
+        steps3 = max(2, args.steps // 4)
+        for prec in ("fp32", "bf16"):
+            log(f"low-rank {n3}x{d3} {prec}: steps {steps3}")
+            lr[prec] = run_workload(X3, W3, K3, L3, prec, steps3, 1)
+            log(f"  {lr[prec]['ms_per_step']:.3f} ms/step")
+        lr["bf16_speedup"] = lr["fp32"]["ms_per_step"] / lr["bf16"]["ms_per_step"]
+        lr["bf16_raw_score_error"] = raw_score_error(X3[:65536].contiguous(), W3, K3, L3, "bf16")
+        extra["low_rank_1024"] = lr
+        del X3
+        torch.cuda.empty_cache()
 
     base = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         base = cpu_baseline(X, W, K, L)
 
     out = {
         "metric": "points/s insert+score (K=15,L=50)",
-        "value": value,
+        "value": head["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -134,13 +200,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "connection-log 494021x120, K=15, L=50, FP32 + FP64 refine",
                    "n": n, "d": d, "K": K, "L": L, "precision": "fp32", "refine": True},
-        "roofline": roof,
+        "roofline": head["roofline"],
         "cpu_baseline": base,
-        "phase_ms_per_step": phases,
-        "refined_bit_frac": cnt["bits_refined"] / max(1, cnt["bits_hashed"]),
-        "flagged": int(flags.sum().item()),
-        "tau": th["tau"],
+        "phase_ms_per_step": head["phase_ms_per_step"],
+        "refined_bit_frac": head["refined_bit_frac"],
+        "flagged": head["flagged"],
+        "tau": head["tau"],
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

@@ -168,13 +168,14 @@ float host_bf16_val(uint16_t h) {
     return x;
 }
 
-int pick_tw(int L, bool allow8) {
-    // Fewest padded tables; ties go to the wider tile.
+int pick_tw(int L, bool fp32) {
+    // Fewest padded tables; ties go to the wider tile.  The split-BF16 kernel holds two
+    // accumulator chains and is built for TW <= 4.
     const int cand[] = {5, 4, 8, 2, 1};
-    int best = 5;
+    int best = fp32 ? 5 : 4;
     long best_pad = -1;
     for (int tw : cand) {
-        if (tw == 8 && !allow8) continue;
+        if (!fp32 && tw > 4) continue;
         const long tiles = (L + 2 * tw - 1) / (2 * tw);
         const long pad = tiles * 2 * tw - L;
         if (best_pad < 0 || pad < best_pad) {
@@ -246,7 +247,7 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     r.list_cap = c->list_cap;
     r.counters = c->rcnt;
     Bracket br(c, s, CLS_REFINE, n);
-    return check(c, launch_refine(r, (int64_t)c->list_cap, s));
+    return check(c, launch_refine(r, (int64_t)c->list_cap, vec, s));
 }
 
 ace_status update_rows(ace_ctx c, const float* X, int64_t n, int sign, hipStream_t s) {

@@ -75,7 +75,7 @@ struct DevThresh {
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
 hipError_t launch_hash_bf16(const HashArgs& a, int TW, bool vec, hipStream_t s);
-hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, hipStream_t s);
+hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
 // sign = +1 insert, -1 delete
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
                                int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s);

@@ -23,7 +23,8 @@
 // projection is queued for the FP64 pass, exactly as in the FP32 kernel.
 //
 // Tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns); workgroup tile 128 rows
-// x 2*TW tables; per wave 64 rows x TW tables, 2 x 4 x TW accumulators of 16x16.
+// x 2*TW tables (TW <= 4); per wave 64 rows x TW tables, 2 x 4 x TW accumulators of
+// 16x16.  The register budget (256 per lane) keeps two waves per SIMD.
 // The FP32 X tile is converted to hi/lo in registers on its way to LDS, together
 // with the three row norms (FP32 sums of squares, rounded up at the end).
 #include "ace_internal.h"
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void hash_bf16_kernel(const HashArgs a) {
     constexpr int NB = 32 * TW;
     __shared__ uint16_t Xh[BM * LDSB], Xl[BM * LDSB];
     __shared__ uint16_t Wh[NB * LDSB], Wl[NB * LDSB];
-    __shared__ float rowA[BM], rowB[BM], rowC[BM];
+    __shared__ __attribute__((aligned(16))) float rowA[BM], rowB[BM], rowC[BM];
 
     const int64_t bid = blockIdx.x;
     const int64_t xcd = bid & 7, local = bid >> 3;
@@ -87,77 +88,76 @@ __global__ __launch_bounds__(256) void hash_bf16_kernel(const HashArgs a) {
             accc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
         }
 
-    // Column bound factors of this wave's tables, read early.
-    float cA[TW], cB[TW], cC[TW], cE[TW];
-#pragma unroll
-    for (int t = 0; t < TW; ++t) {
-        const int cp = col0 + (wn * TW + t) * 16 + (lane & 15);
-        cA[t] = a.wbA[cp];
-        cB[t] = a.wbB[cp];
-        cC[t] = a.wbC[cp];
-        cE[t] = a.wbE[cp];
-    }
-
     const int lr = tid >> 1, lk = (tid & 1) * 16;
     const int64_t grow_ld = row0 + lr;
     const bool row_ok = grow_ld < a.n;
     const float* xrow = a.X + (row_ok ? grow_ld : 0) * (int64_t)a.d;
     float sA = 0.f, sB = 0.f, sC = 0.f;
 
-    for (int k0 = 0; k0 < a.d; k0 += BK) {
-        float v[16];
+    // The next chunk's X values and W quads are fetched into registers while the
+    // current chunk's MFMAs run.
+    float xv[16];
+    s4v whv[TW], wlv[TW];
+    auto gload = [&](int k0) {
         if (VEC) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = k0 + lk + 4 * q;
                 f4 t = f4{0.f, 0.f, 0.f, 0.f};
                 if (row_ok && k < a.d) t = *reinterpret_cast<const f4*>(xrow + k);
-                v[4 * q] = t[0];
-                v[4 * q + 1] = t[1];
-                v[4 * q + 2] = t[2];
-                v[4 * q + 3] = t[3];
+                xv[4 * q] = t[0];
+                xv[4 * q + 1] = t[1];
+                xv[4 * q + 2] = t[2];
+                xv[4 * q + 3] = t[3];
             }
         } else {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int k = k0 + lk + e;
-                v[e] = (row_ok && k < a.d) ? xrow[k] : 0.f;
+                xv[e] = (row_ok && k < a.d) ? xrow[k] : 0.f;
             }
         }
-        uint16_t hb[16], lb[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            hb[e] = bf16_bits(v[e]);
-            const float hv = bf16_val(hb[e]);
-            const float r1 = v[e] - hv;  // exact
-            lb[e] = bf16_bits(r1);
-            const float lv = bf16_val(lb[e]);
-            const float r2 = r1 - lv;    // exact
-            sA = fmaf(hv, hv, sA);
-            sB = fmaf(lv, lv, sB);
-            sC = fmaf(r2, r2, sC);
+        for (int s = 0; s < TW; ++s) {
+            const int q = tid + 256 * s;
+            const int64_t gi = (int64_t)(col0 + (q >> 3)) * a.DP + k0 + (q & 7) * 4;
+            whv[s] = *reinterpret_cast<const s4v*>(a.Wh + gi);
+            wlv[s] = *reinterpret_cast<const s4v*>(a.Wl + gi);
         }
+    };
+
+    gload(0);
+    for (int k0 = 0; k0 < a.d; k0 += BK) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             s8v ph, pl;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                ph[e] = (short)hb[8 * h + e];
-                pl[e] = (short)lb[8 * h + e];
+                const float x = xv[8 * h + e];
+                const uint16_t hb = bf16_bits(x);
+                const float hv = bf16_val(hb);
+                const float r1 = x - hv;  // exact
+                const uint16_t lb = bf16_bits(r1);
+                const float lv = bf16_val(lb);
+                const float r2 = r1 - lv;  // exact
+                sA = fmaf(hv, hv, sA);
+                sB = fmaf(lv, lv, sB);
+                sC = fmaf(r2, r2, sC);
+                ph[e] = (short)hb;
+                pl[e] = (short)lb;
             }
             *reinterpret_cast<s8v*>(Xh + lr * LDSB + lk + 8 * h) = ph;
             *reinterpret_cast<s8v*>(Xl + lr * LDSB + lk + 8 * h) = pl;
         }
-        // W tile: NB columns x 32 k, hi and lo, as 8-byte quads of 4 bf16.
 #pragma unroll
         for (int s = 0; s < TW; ++s) {
             const int q = tid + 256 * s;
-            const int col = q >> 3, kq = (q & 7) * 4;
-            const int64_t gi = (int64_t)(col0 + col) * a.DP + k0 + kq;
-            *reinterpret_cast<s4v*>(Wh + col * LDSB + kq) = *reinterpret_cast<const s4v*>(a.Wh + gi);
-            *reinterpret_cast<s4v*>(Wl + col * LDSB + kq) = *reinterpret_cast<const s4v*>(a.Wl + gi);
+            const int off = (q >> 3) * LDSB + (q & 7) * 4;
+            *reinterpret_cast<s4v*>(Wh + off) = whv[s];
+            *reinterpret_cast<s4v*>(Wl + off) = wlv[s];
         }
         __syncthreads();
+        if (k0 + BK < a.d) gload(k0 + BK);
         // Lane l supplies k = 8*(l>>4) .. +7 of row/column (l & 15) for one 16x16x32 step.
         bf8 ah[4], al[4];
 #pragma unroll
@@ -201,21 +201,29 @@ __global__ __launch_bounds__(256) void hash_bf16_kernel(const HashArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e)
         rok |= (row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3) < a.n) ? (1u << e) : 0u;
+    f4 rA[4], rB[4], rC[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int lrow = wm * 64 + 16 * b + 4 * kin;
+        rA[b] = *reinterpret_cast<const f4*>(rowA + lrow);
+        rB[b] = *reinterpret_cast<const f4*>(rowB + lrow);
+        rC[b] = *reinterpret_cast<const f4*>(rowC + lrow);
+    }
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         const int table = (col0 >> 4) + wn * TW + t;
         const int cp = col0 + (wn * TW + t) * 16 + cl;
+        const float cA = a.wbA[cp], cB = a.wbB[cp], cC = a.wbC[cp], cE = a.wbE[cp];
         f4 p[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) p[b] = accm[b][t] + accc[b][t];
         uint32_t umask = 0;
-        if (a.refine && cA[t] >= 0.f) {
+        if (a.refine && cA >= 0.f) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int lrow = wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
-                float thr = fmaf(rowA[lrow], cA[t], cE[t]);
-                thr = fmaf(rowB[lrow], cB[t], thr);
-                thr = fmaf(rowC[lrow], cC[t], thr);
+                float thr = fmaf(rA[e >> 2][e & 3], cA, cE);
+                thr = fmaf(rB[e >> 2][e & 3], cB, thr);
+                thr = fmaf(rC[e >> 2][e & 3], cC, thr);
                 umask |= !(fabsf(p[e >> 2][e & 3]) > thr) ? (1u << e) : 0u;
             }
             umask &= rok;
@@ -287,7 +295,6 @@ hipError_t launch_hash_bf16(const HashArgs& a, int TW, bool vec, hipStream_t s) 
         case 1: return launch_tw<1>(a, vec, s);
         case 2: return launch_tw<2>(a, vec, s);
         case 4: return launch_tw<4>(a, vec, s);
-        case 5: return launch_tw<5>(a, vec, s);
         default: return hipErrorInvalidValue;
     }
 }

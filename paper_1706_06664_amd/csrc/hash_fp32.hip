@@ -236,6 +236,7 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
 // The FP64 sum runs over ascending t from the FP32 inputs; the code bit is set or
 // cleared with a 32-bit atomic on the word holding the code (the workspace is padded
 // so that word never leaves it).  refined (optional, same layout) gets the bit marked.
+template <bool VEC>
 __global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
     const u64 n_ent = min(*a.list_count, a.list_cap);
     uint32_t n_ref = 0, n_flip = 0;
@@ -247,7 +248,26 @@ __global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
         const float* xr = a.X + row * (int64_t)a.d;
         const float* wr = a.Wt + (int64_t)cp * a.DP;
         double s = 0.0;
-        for (int u = 0; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
+        int u = 0;
+        if (VEC) {
+            // 16-byte loads, four in flight; the additions still run in ascending t.
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            for (; u + 16 <= a.d; u += 16) {
+                const f4 x0 = *reinterpret_cast<const f4*>(xr + u), w0 = *reinterpret_cast<const f4*>(wr + u);
+                const f4 x1 = *reinterpret_cast<const f4*>(xr + u + 4), w1 = *reinterpret_cast<const f4*>(wr + u + 4);
+                const f4 x2 = *reinterpret_cast<const f4*>(xr + u + 8), w2 = *reinterpret_cast<const f4*>(wr + u + 8);
+                const f4 x3 = *reinterpret_cast<const f4*>(xr + u + 12), w3 = *reinterpret_cast<const f4*>(wr + u + 12);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += (double)x0[q] * (double)w0[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += (double)x1[q] * (double)w1[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += (double)x2[q] * (double)w2[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += (double)x3[q] * (double)w3[q];
+            }
+        }
+        for (; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
         const bool bit = s > 0.0;
         const int table = cp >> 4, k = cp & 15;
         if (table < a.L && k < a.K) {
@@ -287,11 +307,14 @@ hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, hipStream_t s) {
+hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s) {
     int64_t blocks = (max_entries + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(refine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (vec)
+        hipLaunchKernelGGL(refine_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(refine_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
