@@ -99,8 +99,8 @@ def run_workload(Xd, W, K, L, precision, steps, warmup):
     bits = c1["bits_hashed"] - c0["bits_hashed"]
     return {
         "points_per_s": n / (ms / 1e3), "ms_per_step": ms,
-        "phase_ms_per_step": {k: prof[k] / steps for k in ("hash_ms", "refine_ms", "update_ms", "score_ms",
-                                                            "other_ms")},
+        "phase_ms_per_step": {k: prof[k] / steps for k in ("convert_ms", "hash_ms", "refine_ms", "update_ms",
+                                                            "score_ms", "other_ms")},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[precision] / 1e12, "unit": "TFLOP/s",
                      "frac": ach / PEAK[precision], "traffic": None, "kernel": KERNEL[precision],
                      "avg_launch_ms": hash_ms, "rows_per_launch": rows,

@@ -19,6 +19,7 @@ FP32, BF16, FP8E4M3 = 0, 1, 2
 THR_SCORED, THR_CONST, THR_TABLE = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "e4m3": FP8E4M3}
 _MODES = {"scored": THR_SCORED, "const": THR_CONST, "table": THR_TABLE}
+_BOUND = {"measured": 0, "generic": 1}
 
 STATUS = {0: "ACE_OK", 1: "ACE_E_INVALID", 2: "ACE_E_NOMEM", 3: "ACE_E_OVERFLOW", 4: "ACE_E_EMPTY",
           5: "ACE_E_DEVICE", 6: "ACE_E_STATE"}
@@ -40,7 +41,8 @@ class AceError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("max_batch_rows", ctypes.c_int64), ("mem_budget", ctypes.c_int64)]
+                ("max_batch_rows", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
+                ("bound_model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Thresh(ctypes.Structure):
@@ -54,7 +56,8 @@ class Profile(ctypes.Structure):
                 ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64),
                 ("score_ms", ctypes.c_double), ("score_launches", ctypes.c_int64),
                 ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64),
-                ("refine_ms", ctypes.c_double), ("refine_launches", ctypes.c_int64)]
+                ("refine_ms", ctypes.c_double), ("refine_launches", ctypes.c_int64),
+                ("convert_ms", ctypes.c_double), ("convert_launches", ctypes.c_int64)]
 
 
 class Counters(ctypes.Structure):
@@ -135,7 +138,7 @@ class ACE:
     """L count arrays of 2^K counters on one GPU, filled and queried through the C ABI."""
 
     def __init__(self, W: np.ndarray, K: int, L: int, precision: str = "fp32", refine: bool = True,
-                 device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0):
+                 device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0, bound: str = "measured"):
         import torch
         W = np.ascontiguousarray(W, dtype=np.float32)
         if W.ndim != 2 or W.shape[1] != K * L:
@@ -144,7 +147,7 @@ class ACE:
         self.d, self.K, self.L = int(W.shape[0]), int(K), int(L)
         self.device = torch.device("cuda", device)
         cfg = Config(self.d, self.K, self.L, _PREC[precision], 1 if refine else 0, device, max_batch_rows,
-                     mem_budget)
+                     mem_budget, _BOUND[bound], 0)
         h = ctypes.c_void_p()
         _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
                "ace_create")

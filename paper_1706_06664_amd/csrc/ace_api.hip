@@ -33,6 +33,9 @@ struct ace_ctx_s {
     uint16_t* ws_codes = nullptr;  // [L][ws_rows] (+ padding for 32-bit patch atomics)
     uint16_t* ws_refined = nullptr;  // same shape, allocated on first request
     int64_t ws_rows = 0;
+    uint16_t* ws_xh = nullptr;     // [ws_rows][DP] split-BF16 rows (BF16 precision)
+    uint16_t* ws_xl = nullptr;
+    float* ws_rown = nullptr;      // [3][ws_rows] row norms
     u64* list = nullptr;           // queue of uncertain projections
     u64* list_count = nullptr;
     u64 list_alloc = 0, list_cap = 0;
@@ -76,7 +79,7 @@ ace_status dev_alloc(ace_ctx c, void** p, size_t bytes) {
     return ACE_OK;
 }
 
-enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3, CLS_REFINE = 4 };
+enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3, CLS_REFINE = 4, CLS_CONVERT = 5 };
 
 hipEvent_t take_event(ace_ctx c) {
     if (!c->pool.empty()) {
@@ -123,7 +126,7 @@ void free_all(ace_ctx c) {
     c->timed.clear();
     c->pool.clear();
     void* ptrs[] = {c->Wt, c->wb, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
-                    c->ws_refined, c->list, c->list_count};
+                    c->ws_refined, c->list, c->list_count, c->ws_xh, c->ws_xl, c->ws_rown};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -224,12 +227,23 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     a.norm_up = (float)(1.0 + ldexp((double)c->DP + 2.0, -23));
     const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
     c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
-    {
+    if (c->cfg.precision == ACE_BF16) {
+        {
+            Bracket br(c, s, CLS_CONVERT, n);
+            st = check(c, launch_convert_bf16(X, n, c->cfg.d, c->DP, vec, c->ws_xh, c->ws_xl, c->ws_rown,
+                                              c->ws_rown + c->ws_rows, c->ws_rown + 2 * c->ws_rows, a.norm_up, s));
+        }
+        if (st) return st;
+        a.Xh = c->ws_xh;
+        a.Xl = c->ws_xl;
+        a.rowA = c->ws_rown;
+        a.rowB = c->ws_rown + c->ws_rows;
+        a.rowC = c->ws_rown + 2 * c->ws_rows;
         Bracket br(c, s, CLS_HASH, n);
-        if (c->cfg.precision == ACE_BF16)
-            st = check(c, launch_hash_bf16(a, c->TW, vec, s));
-        else
-            st = check(c, launch_hash_fp32(a, c->TW, vec, s));
+        st = check(c, launch_hash_bf16(a, c->TW, s));
+    } else {
+        Bracket br(c, s, CLS_HASH, n);
+        st = check(c, launch_hash_fp32(a, c->TW, vec, s));
     }
     if (st || !c->cfg.refine) return st;
     RefineArgs r;
@@ -290,6 +304,8 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     if (cfg->precision != ACE_FP32 && cfg->precision != ACE_BF16) return ACE_E_INVALID;
     if (cfg->refine != 0 && cfg->refine != 1) return ACE_E_INVALID;
     if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
+    if (cfg->bound_model != ACE_BOUND_MEASURED && cfg->bound_model != ACE_BOUND_GENERIC) return ACE_E_INVALID;
+    if (cfg->reserved != 0) return ACE_E_INVALID;
     if ((int64_t)cfg->d > (int64_t)1 << 24) return ACE_E_INVALID;
 
     int ndev = 0;
@@ -317,10 +333,16 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     c->n_tiles_n = (L + 2 * c->TW - 1) / (2 * c->TW);
     c->NP = c->n_tiles_n * 32 * c->TW;
     c->DP = (d + DPAD - 1) / DPAD * DPAD;
-    // gamma_h(2^-23) with h = 2d + 8, rounded up by a relative 2^-16 for the FP32 bound product.
-    const double u = ldexp(1.0, -23), h = 2.0 * d + 8.0;
-    c->gx = (float)(h * u / (1.0 - h * u) * (1.0 + ldexp(1.0, -16)));
-    c->eps_abs = (float)(h * ldexp(1.0, -125));
+    // FP32 bound factor gamma_h(u), rounded up by a relative 2^-16 for the FP32 bound product:
+    //   measured model: exact products, one round-to-nearest per product added -> h = DP + 4, u = 2^-24
+    //   generic model:  up to 6 units of 2^-23 per 4-product instruction        -> h = 2 DP + 8, u = 2^-23
+    {
+        const bool gen = cfg->bound_model == ACE_BOUND_GENERIC;
+        const double u = ldexp(1.0, gen ? -23 : -24);
+        const double h = gen ? 2.0 * c->DP + 8.0 : (double)c->DP + 4.0;
+        c->gx = (float)(h * u / (1.0 - h * u) * (1.0 + ldexp(1.0, -16)));
+        c->eps_abs = (float)((2.0 * c->DP + 8.0) * ldexp(1.0, -125));
+    }
     c->ws_rows = c->cfg.max_batch_rows;
 
     const int64_t B = (int64_t)1 << K;
@@ -331,6 +353,9 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
         st = st ? st : dev_alloc(c, (void**)&c->Wh, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->Wl, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
+        st = st ? st : dev_alloc(c, (void**)&c->ws_xh, sizeof(uint16_t) * (size_t)c->ws_rows * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->ws_xl, sizeof(uint16_t) * (size_t)c->ws_rows * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->ws_rown, sizeof(float) * 3 * (size_t)c->ws_rows);
     }
     st = st ? st : dev_alloc(c, (void**)&c->counts, sizeof(int32_t) * (size_t)L * B);
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
@@ -374,6 +399,13 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
         std::vector<float> f((size_t)4 * c->NP, 0.f);
         for (int cp = 0; cp < c->NP; ++cp) f[cp] = -1.f;
         const double uu = ldexp(1.0, -23), I = (double)c->DP / 32.0, up = 1.0 + ldexp(1.0, -10);
+        // Accumulation error per chain, in units of u = 2^-23 times sum |products|:
+        //   generic:  34 per instruction                    -> main 34 I,     corr 68 I
+        //   measured: 8 x 2^-24 group truncation once, plus  -> main 4 + 2 I,  corr 4 + 4 I
+        //             four roundings of 2^-24 per instruction
+        const bool gen = cfg->bound_model == ACE_BOUND_GENERIC;
+        const double hm = gen ? 34.0 * I : 4.0 + 2.0 * I;
+        const double hc = gen ? 68.0 * I : 4.0 + 4.0 * I;
         for (int j = 0; j < L; ++j)
             for (int k = 0; k < K; ++k) {
                 const int cp = j * KPAD + k;
@@ -397,8 +429,8 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
                 nl = sqrt(nl);
                 nr = sqrt(nr);
                 nw = sqrt(nw);
-                f[cp] = (float)((nr + 34.0 * I * uu * nh + 68.0 * I * uu * nl + 2.0 * uu * (nh + nl)) * up);
-                f[c->NP + cp] = (float)((nl + nr + 68.0 * I * uu * nh + 2.0 * uu * nh) * up);
+                f[cp] = (float)((nr + hm * uu * nh + hc * uu * nl + 2.0 * uu * (nh + nl)) * up);
+                f[c->NP + cp] = (float)((nl + nr + hc * uu * nh + 2.0 * uu * nh) * up);
                 f[2 * c->NP + cp] = (float)(nw * up);
                 f[3 * c->NP + cp] = (float)(3.0 * ldexp(1.0, -126) * sqrt((double)c->DP) * (nw + 1.0) * up);
             }
@@ -714,6 +746,7 @@ ace_status ace_get_profile(ace_ctx c, ace_profile* out) {
             case CLS_UPDATE: out->update_ms += ms; out->update_launches++; break;
             case CLS_SCORE: out->score_ms += ms; out->score_launches++; break;
             case CLS_REFINE: out->refine_ms += ms; out->refine_launches++; break;
+            case CLS_CONVERT: out->convert_ms += ms; out->convert_launches++; break;
             default: out->other_ms += ms; out->other_launches++; break;
         }
         c->pool.push_back(t.a);

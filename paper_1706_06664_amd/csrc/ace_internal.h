@@ -47,6 +47,11 @@ struct HashArgs {
     const float* wbC;
     const float* wbE;
     float norm_up;         // rounding-up factor of FP32 sums of squares over d terms
+    const uint16_t* Xh;    // [n][DP] bf16 bits of x_h (from the convert pass)
+    const uint16_t* Xl;    // [n][DP] bf16 bits of x_l
+    const float* rowA;     // [n] ||x_h||, ||x_l||, ||rho_x||, rounded up
+    const float* rowB;
+    const float* rowC;
 };
 
 // Arguments of the FP64 pass over the queued projections.
@@ -74,7 +79,9 @@ struct DevThresh {
 
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
-hipError_t launch_hash_bf16(const HashArgs& a, int TW, bool vec, hipStream_t s);
+hipError_t launch_convert_bf16(const float* X, int64_t n, int d, int DP, bool vec, uint16_t* Xh, uint16_t* Xl,
+                               float* rowA, float* rowB, float* rowC, float norm_up, hipStream_t s);
+hipError_t launch_hash_bf16(const HashArgs& a, int TW, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
 // sign = +1 insert, -1 delete
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,

@@ -8,15 +8,16 @@
 // in place.
 //
 // Error bound of an FP32 projection (Higham, Accuracy and Stability of Numerical
-// Algorithms, 2nd ed., Sec. 3.1): every term x_t w_t of a sum of d products passes
-// through at most d+1 roundings of relative size u <= 2^-23 (this covers
-// round-to-nearest and truncation, in any summation order), so
-//   |p32 - p| <= gamma_h(u) sum_t |x_t w_t| <= gamma_h(u) ||x|| ||w||
-// with h = d+1.  The library uses h = 2d + 8 for headroom against accumulation
-// details of the matrix unit it does not rely on, plus an absolute term for
-// flushed subnormals.  Outside the bound the sign of p32 is the sign of p; inside
-// it the FP64 sum over ascending t is taken (products of FP32 values are exact in
-// FP64, so this is the same value a plain FP64 loop produces).
+// Algorithms, 2nd ed., Sec. 3.1): if every term x_t w_t passes through at most h
+// roundings of relative size u, then
+//   |p32 - p| <= gamma_h(u) sum_t |x_t w_t| <= gamma_h(u) ||x|| ||w||.
+// The host passes gamma_h(u) for the context's error model: h = DP + 4 with
+// u = 2^-24 (exact products, one round-to-nearest per product added, as measured on
+// gfx950), or h = 2 DP + 8 with u = 2^-23 (any instruction losing up to 6 units of
+// 2^-23), plus an absolute term for flushed subnormals.  Outside the bound the sign
+// of p32 is the sign of p; inside it the FP64 sum over ascending t is taken (products
+// of FP32 values are exact in FP64, so this is the same value a plain FP64 loop
+// produces).
 //
 // Tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns).  A workgroup tile is
 // 128 rows x 2*TW tables (32*TW padded columns); each wave holds 64 rows x TW

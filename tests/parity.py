@@ -104,3 +104,65 @@ def full_parity(X: np.ndarray, W: np.ndarray, K: int, L: int, device="cuda", **a
             "bits_refined": cnt["bits_refined"], "bits_flipped": cnt["bits_flipped"],
             "bits_hashed": cnt["bits_hashed"], "flagged": int(flags_g.sum()), "mu": th_g["mu"],
             "sigma": th_g["sigma"], "tau": th_g["tau"]}
+
+
+def adversarial_rows(X: np.ndarray, W: np.ndarray, n_near: int, n_cancel: int, seed: int) -> np.ndarray:
+    """Rows built to sit near the sign boundary of chosen projection columns:
+    - near-orthogonal: a data row with its component along column c removed (in FP64,
+      then rounded to FP32), so w_c^T x is tiny;
+    - cancelling: two large terms x_i w_ic = 1 and x_j w_jc = -1 plus noise of 1e-3 on the
+      other coordinates, so the running sum passes through magnitudes far above |w_c^T x|.
+    Returns the rows appended to X (float32)."""
+    rng = np.random.default_rng(seed)
+    n, d = X.shape
+    ncol = W.shape[1]
+    out = [X]
+    near = []
+    for _ in range(n_near):
+        y = X[rng.integers(0, n)].astype(np.float64)
+        c = rng.integers(0, ncol)
+        w = W[:, c].astype(np.float64)
+        near.append(y - (y @ w) / (w @ w) * w)
+    if near:
+        out.append(np.array(near, np.float32))
+    canc = []
+    if d >= 2:
+        for _ in range(n_cancel):
+            c = rng.integers(0, ncol)
+            w = W[:, c].astype(np.float64)
+            i, j = rng.choice(d, 2, replace=False)
+            x = rng.standard_normal(d) * 1e-3
+            x[i] = 1.0 / w[i]
+            x[j] = -1.0 / w[j]
+            canc.append(x)
+        out.append(np.array(canc, np.float32))
+    return np.concatenate(out, axis=0).astype(np.float32)
+
+
+def fp32_bound(X: np.ndarray, W: np.ndarray, model: str) -> np.ndarray:
+    """The FP32-mode refinement bound gamma_h(u) ||x|| ||w|| the library states."""
+    d = X.shape[1]
+    DP = -(-d // 32) * 32
+    h, u = (2 * DP + 8, 2.0 ** -23) if model == "generic" else (DP + 4, 2.0 ** -24)
+    gam = h * u / (1 - h * u)
+    return gam * np.linalg.norm(X.astype(np.float64), axis=1)[:, None] * \
+        np.linalg.norm(W.astype(np.float64), axis=0)[None, :]
+
+
+def raw_flip_report(codes_gpu: np.ndarray, P: np.ndarray, bound: np.ndarray, K: int, L: int) -> dict:
+    """Compare raw GPU bits with FP64 signs; every differing bit must lie inside `bound`."""
+    ref = P > 0
+    flips = viol = 0
+    worst = 0.0
+    for j in range(L):
+        for k in range(K):
+            c = j * K + k
+            gbit = ((codes_gpu[:, j] >> k) & 1).astype(bool)
+            diff = gbit != ref[:, c]
+            flips += int(diff.sum())
+            if diff.any():
+                ratio = np.abs(P[diff, c]) / bound[diff, c]
+                worst = max(worst, float(ratio.max()))
+                viol += int((ratio > 1).sum())
+    return {"raw_flips": flips, "violations": viol, "worst_ratio": worst,
+            "raw_flip_rate": flips / (codes_gpu.shape[0] * K * L)}

@@ -84,47 +84,41 @@ def _bf16_split(a):
     return hi.numpy().astype(np.float64), lo.numpy().astype(np.float64), (r1 - lo).numpy().astype(np.float64)
 
 
-def test_bf16_raw_signs_stay_inside_stated_bound():
-    """Refinement off: raw split-BF16 bits may differ from the FP64 signs only where
-    |p64| is inside the bound A cA + B cB + C cC stated for the kernel."""
-    import torch
-    from paper_1706_06664_amd import ACE, codes_as_uint16
-    rng = np.random.default_rng(9)
-    K, L = 15, 50
-    X, _ = c2_points(n=3000, seed=9)
+def bf16_bound(X, W, model):
+    """The split-BF16 refinement bound A cA + B cB + C cC the library states."""
     d = X.shape[1]
-    W = projection_matrix(d, K, L, 5)
-    near = []
-    for i in range(3000):
-        y = X[rng.integers(0, 3000)].astype(np.float64)
-        c = rng.integers(0, K * L)
-        w = W[:, c].astype(np.float64)
-        near.append((y - (y @ w) / (w @ w) * w).astype(np.float32))
-    X = np.concatenate([X, np.array(near)], axis=0)
-    ace = ACE(W, K, L, precision="bf16", refine=False)
-    cg = codes_as_uint16(ace.hash(torch.from_numpy(X).cuda()))
-    P, _ = oracle.project(X, W)
     xh, xl, xr = _bf16_split(X)
     wh, wl, wr = _bf16_split(W)
     A, B, C = (np.linalg.norm(v, axis=1) for v in (xh, xl, xr))
     nh, nl, nr, nw = (np.linalg.norm(v, axis=0) for v in (wh, wl, wr, W.astype(np.float64)))
     u = 2.0 ** -23
     I = math.ceil(d / 32)
-    cA = nr + 34 * I * u * nh + 68 * I * u * nl + 2 * u * (nh + nl)
-    cB = nl + nr + 68 * I * u * nh + 2 * u * nh
-    bound = A[:, None] * cA[None, :] + B[:, None] * cB[None, :] + C[:, None] * nw[None, :]
-    bits_ref = P > 0
-    flips = viol = 0
-    worst = 0.0
-    for j in range(L):
-        for k in range(K):
-            c = j * K + k
-            gbit = ((cg[:, j] >> k) & 1).astype(bool)
-            diff = gbit != bits_ref[:, c]
-            flips += int(diff.sum())
-            if diff.any():
-                ratio = np.abs(P[diff, c]) / bound[diff, c]
-                worst = max(worst, float(ratio.max()))
-                viol += int((ratio > 1).sum())
-    _say({"raw_flips": flips, "raw_flip_rate": flips / (X.shape[0] * K * L), "worst_ratio": worst})
-    assert viol == 0
+    hm, hc = (34 * I, 68 * I) if model == "generic" else (4 + 2 * I, 4 + 4 * I)
+    cA = nr + hm * u * nh + hc * u * nl + 2 * u * (nh + nl)
+    cB = nl + nr + hc * u * nh + 2 * u * nh
+    return A[:, None] * cA[None, :] + B[:, None] * cB[None, :] + C[:, None] * nw[None, :]
+
+
+@pytest.mark.parametrize("model", ["measured", "generic"])
+@pytest.mark.parametrize("shape", ["connection_log", "low_rank_1024"])
+def test_bf16_raw_signs_stay_inside_stated_bound(model, shape):
+    """Refinement off: raw split-BF16 bits may differ from the FP64 signs only where
+    |p64| is inside the bound stated for the error model (adversarial rows included)."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    from tests.parity import adversarial_rows, raw_flip_report
+    if shape == "connection_log":
+        K, L = 15, 50
+        X0, _ = c2_points(n=3000, seed=9)
+    else:
+        from ace_inputs import low_rank_points_torch
+        K, L = 15, 64
+        X0 = low_rank_points_torch(3000, 1024, seed=19, device="cuda")[0].cpu().numpy()
+    W = projection_matrix(X0.shape[1], K, L, 5)
+    X = adversarial_rows(X0, W, 2000, 2000, seed=9)
+    ace = ACE(W, K, L, precision="bf16", refine=False, bound=model)
+    cg = codes_as_uint16(ace.hash(torch.from_numpy(X).cuda()))
+    P, _ = oracle.project(X, W)
+    rep = raw_flip_report(cg, P, bf16_bound(X, W, model), K, L)
+    _say(rep)
+    assert rep["violations"] == 0
