@@ -89,7 +89,9 @@ typedef struct {
     int32_t refine;          /* 1 (default): every projection whose low-precision value lies
                                 inside its derived error bound is recomputed in FP64 from the
                                 FP32 inputs, so every bit equals sign of the FP64 sum;
-                                0: raw low-precision signs (for flip-rate reports) */
+                                0: raw low-precision signs (for flip-rate reports);
+                                2: raw signs, but the bits inside the bound are counted
+                                (bits_in_bound_unrefined) */
     int32_t device;          /* HIP device ordinal */
     int64_t max_batch_rows;  /* rows hashed per internal chunk; 0 = 1<<20 */
     int64_t mem_budget;      /* device bytes the context may allocate; 0 = unlimited */
@@ -120,6 +122,7 @@ typedef struct {
     uint64_t bits_hashed;    /* projection bits computed (rows * K * L) */
     uint64_t bits_refined;   /* bits recomputed in FP64 */
     uint64_t bits_flipped;   /* refined bits whose sign differed from the low-precision sign */
+    uint64_t bits_in_bound_unrefined;  /* refine = 2: bits inside the bound, left raw */
 } ace_counters;
 
 /* Create a context on cfg->device: copies W (host, FP32 [d][K*L]) and zeroes the L x 2^K

@@ -63,7 +63,8 @@ class Profile(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m_scored", ctypes.c_int64), ("sum_T", ctypes.c_int64),
                 ("sum_T2_lo", ctypes.c_uint64), ("sum_T2_hi", ctypes.c_uint64), ("bits_hashed", ctypes.c_uint64),
-                ("bits_refined", ctypes.c_uint64), ("bits_flipped", ctypes.c_uint64)]
+                ("bits_refined", ctypes.c_uint64), ("bits_flipped", ctypes.c_uint64),
+                ("bits_in_bound_unrefined", ctypes.c_uint64)]
 
 
 _lib = None
@@ -146,7 +147,8 @@ class ACE:
         self.lib = load_library()
         self.d, self.K, self.L = int(W.shape[0]), int(K), int(L)
         self.device = torch.device("cuda", device)
-        cfg = Config(self.d, self.K, self.L, _PREC[precision], 1 if refine else 0, device, max_batch_rows,
+        rmode = int(refine) if not isinstance(refine, bool) else (1 if refine else 0)
+        cfg = Config(self.d, self.K, self.L, _PREC[precision], rmode, device, max_batch_rows,
                      mem_budget, _BOUND[bound], 0)
         h = ctypes.c_void_p()
         _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -20,6 +21,8 @@ struct ace_ctx_s {
 
     float* Wt = nullptr;   // [NP][DP]
     float* wb = nullptr;   // [NP]
+    uint8_t* Wq = nullptr;   // [NP][DP] e4m3 codes of the scaled columns (FP8 precision)
+    uint8_t* ws_xq = nullptr;  // [ws_rows][DP] e4m3 rows (FP8 precision)
     uint16_t* Wh = nullptr;  // [NP][DP] split-BF16 hi / lo (BF16 precision)
     uint16_t* Wl = nullptr;
     float* wbA = nullptr;    // [4][NP] BF16 bound factors (A, B, C, absolute)
@@ -125,7 +128,7 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
+    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->ws_xq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
                     c->ws_refined, c->list, c->list_count, c->ws_xh, c->ws_xl, c->ws_rown};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -169,6 +172,28 @@ float host_bf16_val(uint16_t h) {
     float x;
     memcpy(&x, &u, 4);
     return x;
+}
+
+// OCP e4m3 encoding (bias 7, max 448) with round-to-nearest-even of |v| <= 448, the same
+// rounding the device conversion uses; *q receives the encoded value.
+uint8_t host_e4m3(float v, float* q) {
+    const float a = fabsf(v);
+    const uint8_t s = std::signbit(v) ? 0x80 : 0;
+    if (a < 0x1p-6f) {
+        const float m = nearbyintf(a * 512.f);
+        *q = copysignf(m * 0x1p-9f, v);
+        return (uint8_t)(s | (uint8_t)m);
+    }
+    uint32_t u;
+    memcpy(&u, &a, 4);
+    u += 0x7FFFFu + ((u >> 20) & 1u);
+    u &= 0xFFF00000u;
+    float r;
+    memcpy(&r, &u, 4);
+    *q = copysignf(r, v);
+    const uint32_t E = ((u >> 23) & 0xFFu) - 127u + 7u;
+    const uint32_t M = (u >> 20) & 7u;
+    return (uint8_t)(s | (E << 3) | M);
 }
 
 int pick_tw(int L, bool fp32) {
@@ -227,7 +252,20 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     a.norm_up = (float)(1.0 + ldexp((double)c->DP + 2.0, -23));
     const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
     c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
-    if (c->cfg.precision == ACE_BF16) {
+    if (c->cfg.precision == ACE_FP8E4M3) {
+        {
+            Bracket br(c, s, CLS_CONVERT, n);
+            st = check(c, launch_convert_fp8(X, n, c->cfg.d, c->DP, vec, c->ws_xq, c->ws_rown, c->ws_rown + c->ws_rows,
+                                             a.norm_up, s));
+        }
+        if (st) return st;
+        a.Xq = c->ws_xq;
+        a.Wq = c->Wq;
+        a.rowA = c->ws_rown;
+        a.rowB = c->ws_rown + c->ws_rows;
+        Bracket br(c, s, CLS_HASH, n);
+        st = check(c, launch_hash_fp8(a, c->TW, s));
+    } else if (c->cfg.precision == ACE_BF16) {
         {
             Bracket br(c, s, CLS_CONVERT, n);
             st = check(c, launch_convert_bf16(X, n, c->cfg.d, c->DP, vec, c->ws_xh, c->ws_xl, c->ws_rown,
@@ -245,7 +283,7 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
         Bracket br(c, s, CLS_HASH, n);
         st = check(c, launch_hash_fp32(a, c->TW, vec, s));
     }
-    if (st || !c->cfg.refine) return st;
+    if (st || c->cfg.refine != 1) return st;
     RefineArgs r;
     r.X = X;
     r.d = c->cfg.d;
@@ -301,8 +339,9 @@ const char* ace_version(void) { return "ace-mi355x 0.1 (gfx950)"; }
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) {
     if (!cfg || !W_host || !out) return ACE_E_INVALID;
     if (cfg->d < 1 || cfg->K < 1 || cfg->K > 16 || cfg->L < 1 || cfg->L > 4096) return ACE_E_INVALID;
-    if (cfg->precision != ACE_FP32 && cfg->precision != ACE_BF16) return ACE_E_INVALID;
-    if (cfg->refine != 0 && cfg->refine != 1) return ACE_E_INVALID;
+    if (cfg->precision != ACE_FP32 && cfg->precision != ACE_BF16 && cfg->precision != ACE_FP8E4M3)
+        return ACE_E_INVALID;
+    if (cfg->refine < 0 || cfg->refine > 2) return ACE_E_INVALID;
     if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
     if (cfg->bound_model != ACE_BOUND_MEASURED && cfg->bound_model != ACE_BOUND_GENERIC) return ACE_E_INVALID;
     if (cfg->reserved != 0) return ACE_E_INVALID;
@@ -329,10 +368,11 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     c->cfg = *cfg;
     if (c->cfg.max_batch_rows == 0) c->cfg.max_batch_rows = (int64_t)1 << 20;
     const int d = cfg->d, K = cfg->K, L = cfg->L;
-    c->TW = pick_tw(L, cfg->precision == ACE_FP32);
+    c->TW = pick_tw(L, cfg->precision != ACE_BF16);
     c->n_tiles_n = (L + 2 * c->TW - 1) / (2 * c->TW);
     c->NP = c->n_tiles_n * 32 * c->TW;
-    c->DP = (d + DPAD - 1) / DPAD * DPAD;
+    const int dpad = cfg->precision == ACE_FP8E4M3 ? 128 : DPAD;  // FP8 k-steps are 128 wide
+    c->DP = (d + dpad - 1) / dpad * dpad;
     // FP32 bound factor gamma_h(u), rounded up by a relative 2^-16 for the FP32 bound product:
     //   measured model: exact products, one round-to-nearest per product added -> h = DP + 4, u = 2^-24
     //   generic model:  up to 6 units of 2^-23 per 4-product instruction        -> h = 2 DP + 8, u = 2^-23
@@ -349,6 +389,12 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     ace_status st = ACE_OK;
     st = st ? st : dev_alloc(c, (void**)&c->Wt, sizeof(float) * (size_t)c->NP * c->DP);
     st = st ? st : dev_alloc(c, (void**)&c->wb, sizeof(float) * (size_t)c->NP);
+    if (cfg->precision == ACE_FP8E4M3) {
+        st = st ? st : dev_alloc(c, (void**)&c->Wq, (size_t)c->NP * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
+        st = st ? st : dev_alloc(c, (void**)&c->ws_xq, (size_t)c->ws_rows * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&c->ws_rown, sizeof(float) * 3 * (size_t)c->ws_rows);
+    }
     if (cfg->precision == ACE_BF16) {
         st = st ? st : dev_alloc(c, (void**)&c->Wh, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->Wl, sizeof(uint16_t) * (size_t)c->NP * c->DP);
@@ -361,7 +407,7 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->mom, sizeof(u64) * 4);
-    st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 2);
+    st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
     st = st ? st : dev_alloc(c, (void**)&c->ws_codes, sizeof(uint16_t) * ((size_t)L * c->ws_rows + 2));
@@ -438,13 +484,48 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
         if (e == hipSuccess) e = hipMemcpy(c->Wl, Wl.data(), Wl.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->wbA, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && cfg->precision == ACE_FP8E4M3) {
+        // Per-column power-of-two scale s_c (max |w| / s_c <= 448), e4m3 codes of w / s_c,
+        // and the column factors of the bound (see the FP8 kernel), in scaled units.
+        std::vector<uint8_t> Wq((size_t)c->NP * c->DP, 0);
+        std::vector<float> f((size_t)4 * c->NP, 0.f);
+        for (int cp = 0; cp < c->NP; ++cp) f[cp] = -1.f;
+        const double I = (double)c->DP / 128.0, up = 1.0 + ldexp(1.0, -10);
+        const double hacc = ldexp(1.0, -9) + 8.0 * I * ldexp(1.0, -24);
+        for (int j = 0; j < L; ++j)
+            for (int k = 0; k < K; ++k) {
+                const int cp = j * KPAD + k;
+                float mx = 0.f;
+                for (int t = 0; t < d; ++t) mx = fmaxf(mx, fabsf(W_host[(size_t)t * K * L + (size_t)j * K + k]));
+                int ex = 0;
+                if (mx > 0.f) {
+                    ex = ilogbf(mx / 448.f);
+                    while (ldexpf(mx, -ex) > 448.f) ++ex;
+                }
+                double nq = 0, nd = 0;
+                for (int t = 0; t < d; ++t) {
+                    const float w = ldexpf(W_host[(size_t)t * K * L + (size_t)j * K + k], -ex);
+                    float q;
+                    Wq[(size_t)cp * c->DP + t] = host_e4m3(w, &q);
+                    nq += (double)q * q;
+                    nd += (double)(w - q) * (w - q);
+                }
+                nq = sqrt(nq);
+                nd = sqrt(nd);
+                f[cp] = (float)((nd + hacc * nq) * up);
+                f[c->NP + cp] = (float)((nq + nd) * up);
+                f[3 * c->NP + cp] = (float)((double)c->DP * ldexp(1.0, -140) * (nq + 1.0) * up);
+            }
+        e = hipMemcpy(c->Wq, Wq.data(), Wq.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->wbA, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->wb, wb.data(), wb.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->counts, 0, sizeof(int32_t) * (size_t)L * B);
     if (e == hipSuccess) e = hipMemset(c->S2, 0, sizeof(u64) * (size_t)L);
     if (e == hipSuccess) e = hipMemset(c->S3, 0, sizeof(u64) * 2 * (size_t)L);
     if (e == hipSuccess) e = hipMemset(c->mom, 0, sizeof(u64) * 4);
-    if (e == hipSuccess) e = hipMemset(c->rcnt, 0, sizeof(u64) * 2);
+    if (e == hipSuccess) e = hipMemset(c->rcnt, 0, sizeof(u64) * 4);
     if (e == hipSuccess) e = hipMemset(c->err, 0, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -684,7 +765,7 @@ ace_status ace_get_counters(ace_ctx c, ace_counters* out) {
     if (!out) return ACE_E_INVALID;
     DeviceGuard g(c->cfg.device);
     if ((st = sync_and_check(c))) return st;
-    u64 mom[4], r[2];
+    u64 mom[4], r[4];
     st = check(c, hipMemcpy(mom, c->mom, sizeof(mom), hipMemcpyDeviceToHost));
     if (!st) st = check(c, hipMemcpy(r, c->rcnt, sizeof(r), hipMemcpyDeviceToHost));
     if (st) return st;
@@ -696,6 +777,7 @@ ace_status ace_get_counters(ace_ctx c, ace_counters* out) {
     out->bits_hashed = c->bits_hashed;
     out->bits_refined = r[0];
     out->bits_flipped = r[1];
+    out->bits_in_bound_unrefined = r[2];
     return ACE_OK;
 }
 

@@ -38,7 +38,8 @@ struct HashArgs {
     u64* list;             // queue of uncertain projections: row | column << 32 | raw bit << 63
     u64* list_count;       // entries appended (may exceed list_cap)
     u64 list_cap;
-    u64* counters;         // [0] bits refined, [1] refined bits that flipped (queue-full path)
+    u64* counters;         // [0] bits refined, [1] refined bits that flipped (queue-full path),
+                           // [2] bits inside the bound left unrefined (refine = 2)
     // Split-BF16 operands and bound factors (BF16 kernel only)
     const uint16_t* Wh;    // [NP][DP] bf16 bits of w_h
     const uint16_t* Wl;    // [NP][DP] bf16 bits of w_l
@@ -52,6 +53,8 @@ struct HashArgs {
     const float* rowA;     // [n] ||x_h||, ||x_l||, ||rho_x||, rounded up
     const float* rowB;
     const float* rowC;
+    const uint8_t* Xq;     // [n][DP] e4m3 codes of the scaled rows (FP8 kernel)
+    const uint8_t* Wq;     // [NP][DP] e4m3 codes of the scaled columns
 };
 
 // Arguments of the FP64 pass over the queued projections.
@@ -82,6 +85,9 @@ hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s);
 hipError_t launch_convert_bf16(const float* X, int64_t n, int d, int DP, bool vec, uint16_t* Xh, uint16_t* Xl,
                                float* rowA, float* rowB, float* rowC, float norm_up, hipStream_t s);
 hipError_t launch_hash_bf16(const HashArgs& a, int TW, hipStream_t s);
+hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec, uint8_t* Xq, float* rowA,
+                              float* rowB, float norm_up, hipStream_t s);
+hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
 // sign = +1 insert, -1 delete
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,

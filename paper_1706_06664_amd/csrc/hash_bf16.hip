@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     const int kin = lane >> 4, cl = lane & 15;
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = row0 + wm * 64 + lane;
-    uint32_t n_ref = 0, n_flip = 0;
+    uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
     uint32_t rok = 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e)
@@ -250,6 +250,10 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
                 umask |= !(fabsf(p[e >> 2][e & 3]) > thr) ? (1u << e) : 0u;
             }
             umask &= rok;
+        }
+        if (a.refine == 2) {
+            n_unc += __popc(umask);  // count only: the raw signs stand
+            umask = 0;
         }
         if (__any(umask != 0)) {
             const uint32_t mine = __popc(umask);
@@ -291,11 +295,12 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
         }
         if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
-    if (__any(n_ref != 0)) {
-        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
+    if (__any(n_ref != 0 || n_unc != 0)) {
+        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);
         if (lane == 0) {
-            atomicAdd(&a.counters[0], (u64)r);
+            if (r) atomicAdd(&a.counters[0], (u64)r);
             if (f) atomicAdd(&a.counters[1], (u64)f);
+            if (uc) atomicAdd(&a.counters[2], (u64)uc);
         }
     }
 }

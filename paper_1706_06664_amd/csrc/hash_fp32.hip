@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
     }
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = row0 + wm * 64 + lane;  // the row whose codes this lane stores
-    uint32_t n_ref = 0, n_flip = 0;                // projections decided in place (queue full)
+    uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         const int table = (col0 >> 4) + wn * TW + t;
@@ -181,6 +181,10 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
                 umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;  // NaN is uncertain too
             }
             umask &= rok;
+        }
+        if (a.refine == 2) {
+            n_unc += __popc(umask);  // count only: the raw signs stand
+            umask = 0;
         }
         if (__any(umask != 0)) {
             // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave.
@@ -224,11 +228,12 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
         }
         if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
-    if (__any(n_ref != 0)) {
-        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
+    if (__any(n_ref != 0 || n_unc != 0)) {
+        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);
         if (lane == 0) {
-            atomicAdd(&a.counters[0], (u64)r);
+            if (r) atomicAdd(&a.counters[0], (u64)r);
             if (f) atomicAdd(&a.counters[1], (u64)f);
+            if (uc) atomicAdd(&a.counters[2], (u64)uc);
         }
     }
 }

@@ -1,0 +1,315 @@
+// SRP hashing on FP8 (OCP e4m3) MFMA with power-of-two row and column scales
+// (Sec. 2.1 signed random projections, Sec. 3.2 K-bit codes),
+// v_mfma_scale_f32_16x16x128_f8f6f4 with unit block scales, FP32 accumulate.
+//
+// Each row is scaled by s_i = 2^ceil(log2(max|x_i| / 448)) and each W column by s_c
+// likewise, so every scaled value fits e4m3 (max 448) and scaling is exact.  The
+// kernel computes p^ = sum_t x^_t w^_t in scaled units; positive scales do not change
+// the sign, so p^ decides the bit.  With x/s = x^ + dx and w/s_c = w^ + dw (both
+// remainders exact in FP32):
+//     |p/(s_i s_c) - p^| <= ||x^|| ||dw|| + ||dx|| ||w^|| + ||dx|| ||dw|| + acc
+// where acc bounds the accumulation.  On gfx950 the unit aligns the 8 products of a
+// k-group to the largest and keeps about 13 bits below it (measured), then adds group
+// sums to the FP32 accumulator with round-to-nearest, so
+//     acc <= (2^-9 + 8 I 2^-24) sum |x^ w^|,  I = DP / 128 instructions
+// (twice the measured in-group loss).  The bound is A cA + B cB + eps with
+// A = ||x^||, B = ||dx|| and cA = ||dw|| + (2^-9 + 8 I 2^-24) ||w^||,
+// cB = ||w^|| + ||dw||, rounded up by the host.  Projections inside it are queued for
+// the FP64 pass (refine = 1) or only counted (refine = 2).
+//
+// Tiling as in the BF16 kernel: 256 threads = 2 x 2 waves, 128 rows x 2*TW tables per
+// workgroup, k-steps of 128 (one MFMA); each lane supplies 32 consecutive k of one row
+// or column.
+#include "ace_internal.h"
+
+namespace ace {
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int BKB = 128;            // k per step (bytes per row of the tile)
+constexpr int LDSR = BKB + 16;      // padded LDS row stride in bytes
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane) {
+    const int r = lane & 3, g = (lane & 15) >> 2;
+    u64 m = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
+    return (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// OCP e4m3 (bias 7, max 448, subnormals q * 2^-9) with round-to-nearest-even, for
+// |v| <= 448.  Returns the code and the value it encodes.
+__device__ inline uint32_t e4m3_encode(float v, float& q) {
+    const uint32_t s = (__float_as_uint(v) >> 24) & 0x80u;
+    const float a = fabsf(v);
+    if (a < 0x1p-6f) {
+        const float m = rintf(a * 512.f);  // 0..8; 8 is the smallest normal, same code
+        q = copysignf(m * 0x1p-9f, v);
+        return s | (uint32_t)m;
+    }
+    uint32_t u = __float_as_uint(a);
+    u += 0x7FFFFu + ((u >> 20) & 1u);      // round the mantissa to 3 bits
+    u &= 0xFFF00000u;
+    q = copysignf(__uint_as_float(u), v);
+    const uint32_t E = ((u >> 23) & 0xFFu) - 127u + 7u;
+    const uint32_t M = (u >> 20) & 7u;
+    return s | (E << 3) | M;
+}
+
+// Convert + row norms: one wave per row.  Pass 1 finds max|x|; pass 2 scales by the
+// power of two, encodes, writes Xq [n][DP] bytes and A = ||x^||, B = ||dx||.
+template <bool VEC>
+__global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restrict__ X, int64_t n, int d, int DP,
+                                                          uint8_t* __restrict__ Xq, float* __restrict__ rowA,
+                                                          float* __restrict__ rowB, float norm_up) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const float* xr = X + row * (int64_t)d;
+    float mx = 0.f;
+    for (int k = lane; k < d; k += 64) mx = fmaxf(mx, fabsf(xr[k]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    // scale exponent: smallest e with max|x| * 2^-e <= 448
+    int e = 0;
+    if (mx > 0.f) {
+        e = ilogbf(mx / 448.f);
+        if (ldexpf(mx, -e) > 448.f) ++e;
+        if (ldexpf(mx, -e) > 448.f) ++e;
+    }
+    float sA = 0.f, sB = 0.f;
+    for (int k0 = 16 * lane; k0 < DP; k0 += 1024) {
+        uint32_t w4[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = k0 + 4 * q4 + b;
+                const float x = (k < d) ? ldexpf(xr[k], -e) : 0.f;
+                float qv;
+                const uint32_t code = e4m3_encode(x, qv);
+                const float dx = x - qv;  // exact
+                sA = fmaf(qv, qv, sA);
+                sB = fmaf(dx, dx, sB);
+                word |= code << (8 * b);
+            }
+            w4[q4] = word;
+        }
+        *reinterpret_cast<i4v*>(Xq + row * (int64_t)DP + k0) = i4v{(int)w4[0], (int)w4[1], (int)w4[2], (int)w4[3]};
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sA += __shfl_xor(sA, off, 64);
+        sB += __shfl_xor(sB, off, 64);
+    }
+    if (lane == 0) {
+        rowA[row] = sqrtf(sA * norm_up) * (1.f + 0x1p-20f);
+        rowB[row] = sqrtf(sB * norm_up) * (1.f + 0x1p-20f);
+    }
+}
+
+template <int TW>
+__global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
+    constexpr int NB = 32 * TW;
+    __shared__ __attribute__((aligned(16))) uint8_t Xs[BM * LDSR];
+    __shared__ __attribute__((aligned(16))) uint8_t Ws[NB * LDSR];
+
+    const int64_t bid = blockIdx.x;
+    const int64_t xcd = bid & 7, local = bid >> 3;
+    const int64_t tile_n = local % a.n_tiles_n;
+    const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
+    if (tile_m >= a.n_tiles_m) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t row0 = tile_m * BM;
+    const int col0 = (int)tile_n * NB;
+
+    f4 acc[4][TW];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // X tile: 128 rows x 128 bytes; thread -> row tid/2, 64 bytes at (tid&1)*64.
+    // W tile: NB columns x 128 bytes as 16-byte quads, TW/2 per thread (TW even) or
+    // spread over the block otherwise.
+    const int lr = tid >> 1, lk = (tid & 1) * 64;
+    const int64_t grow_ld = row0 + lr;
+    const bool row_ok = grow_ld < a.n;
+    const uint8_t* xq = a.Xq + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
+    constexpr int WQ = NB * (BKB / 16);          // 16-byte quads in the W tile
+    constexpr int WPT = (WQ + 255) / 256;        // per thread
+    i4v xv[4];
+    i4v wv[WPT];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            xv[q] = row_ok ? *reinterpret_cast<const i4v*>(xq + k0 + 16 * q) : i4v{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < WPT; ++s) {
+            const int q = tid + 256 * s;
+            if (q < WQ) {
+                const int col = q >> 3, kq = (q & 7) * 16;
+                wv[s] = *reinterpret_cast<const i4v*>(a.Wq + (int64_t)(col0 + col) * a.DP + k0 + kq);
+            }
+        }
+    };
+
+    gload(0);
+    for (int k0 = 0; k0 < a.DP; k0 += BKB) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<i4v*>(Xs + lr * LDSR + lk + 16 * q) = xv[q];
+#pragma unroll
+        for (int s = 0; s < WPT; ++s) {
+            const int q = tid + 256 * s;
+            if (q < WQ) *reinterpret_cast<i4v*>(Ws + (q >> 3) * LDSR + (q & 7) * 16) = wv[s];
+        }
+        __syncthreads();
+        if (k0 + BKB < a.DP) gload(k0 + BKB);
+        // Lane l supplies 32 consecutive k (bytes 32*(l>>4) ..) of row/column (l & 15).
+        i8v af[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint8_t* p = Xs + (wm * 64 + 16 * b + (lane & 15)) * LDSR + 32 * (lane >> 4);
+            const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 16);
+            af[b] = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            const uint8_t* p = Ws + ((wn * TW + t) * 16 + (lane & 15)) * LDSR + 32 * (lane >> 4);
+            const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 16);
+            const i8v bf = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[b][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[b], bf, acc[b][t], 0, 0, 0, 127, 0,
+                                                                             127);
+        }
+        __syncthreads();
+    }
+
+    const int kin = lane >> 4, cl = lane & 15;
+    const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
+    const int64_t orow = row0 + wm * 64 + lane;
+    uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
+    uint32_t rok = 0;
+    float rA[16], rB[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        int64_t g = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
+        rok |= (g < a.n) ? (1u << e) : 0u;
+        g = g < a.n ? g : a.n - 1;
+        rA[e] = a.rowA[g];
+        rB[e] = a.rowB[g];
+    }
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const int table = (col0 >> 4) + wn * TW + t;
+        const int cp = col0 + (wn * TW + t) * 16 + cl;
+        const float cA = a.wbA[cp], cB = a.wbB[cp], cE = a.wbE[cp];
+        uint32_t umask = 0;
+        if (a.refine && cA >= 0.f) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                float thr = fmaf(rA[e], cA, cE);
+                thr = fmaf(rB[e], cB, thr);
+                umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;
+            }
+            umask &= rok;
+        }
+        if (a.refine == 2) {
+            n_unc += __popc(umask);  // count only: the raw signs stand
+            umask = 0;
+        }
+        if (__any(umask != 0)) {
+            const uint32_t mine = __popc(umask);
+            uint32_t incl = mine;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            u64 base = 0;
+            if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
+            base = __shfl(base, 0, 64);
+            u64 slot = base + (incl - mine);
+            for (int e = 0; e < 16; ++e) {
+                if (!((umask >> e) & 1u)) continue;
+                const int64_t grow = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
+                const float pv = acc[e >> 2][t][e & 3];
+                if (slot < a.list_cap) {
+                    a.list[slot] = (u64)(uint32_t)grow | ((u64)cp << 32) | ((pv > 0.f) ? (1ull << 63) : 0ull);
+                } else {
+                    const float* xr = a.X + grow * (int64_t)a.d;
+                    const float* wr = a.Wt + (int64_t)cp * a.DP;
+                    double sacc = 0.0;
+                    for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
+                    n_ref += 1u;
+                    n_flip += ((sacc > 0.0) != (pv > 0.f)) ? 1u : 0u;
+                    acc[e >> 2][t][e & 3] = sacc > 0.0 ? 1.f : -1.f;
+                }
+                ++slot;
+            }
+        }
+        uint32_t code = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
+                                            __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
+            code = (kin == b) ? cb : code;
+        }
+        if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+    }
+    if (__any(n_ref != 0 || n_unc != 0)) {
+        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);
+        if (lane == 0) {
+            if (r) atomicAdd(&a.counters[0], (u64)r);
+            if (f) atomicAdd(&a.counters[1], (u64)f);
+            if (uc) atomicAdd(&a.counters[2], (u64)uc);
+        }
+    }
+}
+
+template <int TW>
+hipError_t launch_tw(const HashArgs& a, hipStream_t s) {
+    const int64_t groups = (a.n_tiles_m + 7) / 8;
+    const int64_t blocks = groups * 8 * a.n_tiles_n;
+    hipLaunchKernelGGL((hash_fp8_kernel<TW>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec, uint8_t* Xq, float* rowA,
+                              float* rowB, float norm_up, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 3) / 4;
+    if (vec)
+        hipLaunchKernelGGL(convert_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xq, rowA,
+                           rowB, norm_up);
+    else
+        hipLaunchKernelGGL(convert_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xq, rowA,
+                           rowB, norm_up);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s) {
+    switch (TW) {
+        case 1: return launch_tw<1>(a, s);
+        case 2: return launch_tw<2>(a, s);
+        case 4: return launch_tw<4>(a, s);
+        case 5: return launch_tw<5>(a, s);
+        case 8: return launch_tw<8>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ace
