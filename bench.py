@@ -75,14 +75,15 @@ def cpu_baseline(X, W, K, L, target_s=12.0):
                       f"hash+score+threshold+flags, {t2:.1f} s on {threads} OpenMP threads"}
 
 
-def run_workload(Xd, W, K, L, precision, steps, warmup):
-    """Time `steps` full steps; return timing, per-kernel event timing and counters."""
+def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None):
+    """Time `steps` full steps; return timing, per-kernel event timing and counters.
+    If `keep` is a dict, the last step's T (int32, device) is stored in keep["T"]."""
     import torch
     from paper_1706_06664_amd import ACE
     n, d = Xd.shape
     s = torch.empty(n, dtype=torch.float32, device=Xd.device)
     T = torch.empty(n, dtype=torch.int32, device=Xd.device)
-    ace = ACE(W, K, L, precision=precision, device=0)
+    ace = ACE(W, K, L, precision=precision, device=0, refine=refine)
 
     def step():
         ace.reset()
@@ -107,11 +108,14 @@ def run_workload(Xd, W, K, L, precision, steps, warmup):
     prof = ace.profile()
     c1 = ace.counters()
     ace.close()
+    if keep is not None:
+        keep["T"] = T
     ms = (t1 - t0) * 1e3 / steps
     hash_ms = prof["hash_ms"] / max(1, prof["hash_launches"])
     rows = prof["hash_rows"] / max(1, prof["hash_launches"])
     flop = 2.0 * rows * d * K * L
     executed = flop * (16.0 / K) * (3.0 if precision == "bf16" else 1.0)
+    kernel = {"fp32": "hash_fp32_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}[precision]
     ach = flop / (hash_ms / 1e3)
     bits = c1["bits_hashed"] - c0["bits_hashed"]
     return {
@@ -119,11 +123,12 @@ def run_workload(Xd, W, K, L, precision, steps, warmup):
         "phase_ms_per_step": {k: prof[k] / steps for k in ("convert_ms", "hash_ms", "refine_ms", "update_ms",
                                                             "score_ms", "other_ms")},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[precision] / 1e12, "unit": "TFLOP/s",
-                     "frac": ach / PEAK[precision], "traffic": None, "kernel": KERNEL[precision],
+                     "frac": ach / PEAK[precision], "traffic": None, "kernel": kernel,
                      "avg_launch_ms": hash_ms, "rows_per_launch": rows,
                      "executed_frac": executed / (hash_ms / 1e3) / PEAK[precision]},
         "refined_bit_frac": (c1["bits_refined"] - c0["bits_refined"]) / max(1, bits),
         "raw_flip_rate": (c1["bits_flipped"] - c0["bits_flipped"]) / max(1, bits),
+        "in_bound_unrefined_frac": (c1["bits_in_bound_unrefined"] - c0["bits_in_bound_unrefined"]) / max(1, bits),
         "flagged": int(flags.sum().item()), "tau": th["tau"],
     }
 
@@ -145,6 +150,51 @@ def raw_score_error(Xs, W, K, L, precision):
     rel = np.abs(raw - ref) / np.maximum(ref, 1.0)
     return {"rows": int(Xs.shape[0]), "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
             "rows_changed": int((raw != ref).sum())}
+
+
+def popcount_xor(a, b):
+    """Number of differing bits between two int16 device tensors of codes."""
+    import torch
+    table = torch.tensor([bin(i).count("1") for i in range(256)], dtype=torch.int64, device=a.device)
+    x = torch.bitwise_xor(a, b).contiguous().view(torch.uint8)
+    return int(table[x.long()].sum().item())
+
+
+def heavy_tail_runs(steps):
+    """Heavy-tailed 1,000,000 x 4096 rows, K = 16, L = 100: FP32 and split-BF16 refined steps,
+    and FP8 e4m3 with raw signs (refine = 2 also counts the bits inside the FP8 bound).  The
+    FP8 raw flip rate and score error are taken against the FP32 refined codes and scores,
+    which equal the FP64 signs (GPU tests)."""
+    import numpy as np
+    import torch
+    from ace_inputs import heavy_tail_points_torch, projection_matrix
+    from paper_1706_06664_amd import ACE
+    n4, d4, K4, L4 = 1_000_000, 4096, 16, 100
+    X4, _ = heavy_tail_points_torch(n4, d4, seed=4, device="cuda:0")
+    W4 = projection_matrix(d4, K4, L4, 1706066644)
+    out = {"workload": f"heavy-tail t(3) {n4}x{d4}, K={K4}, L={L4}"}
+    keep = {}
+    for prec, refine in (("fp32", 1), ("bf16", 1), ("fp8", 2)):
+        log(f"heavy-tail {n4}x{d4} {prec} refine={refine}: steps {steps}")
+        k = {}
+        out[prec] = run_workload(X4, W4, K4, L4, prec, steps, 1, refine=refine, keep=k)
+        keep[prec] = k["T"].clone()
+        log(f"  {out[prec]['ms_per_step']:.3f} ms/step")
+    c32 = ACE(W4, K4, L4, precision="fp32").hash(X4)
+    c8 = ACE(W4, K4, L4, precision="fp8", refine=0).hash(X4)
+    flips = popcount_xor(c32, c8)
+    t32 = keep["fp32"].double()
+    t8 = keep["fp8"].double()
+    rel = (t8 - t32).abs() / t32.clamp_min(1.0)
+    out["fp8_raw_flip_rate"] = flips / (n4 * K4 * L4)
+    out["fp8_raw_score_error"] = {"max_rel": float(rel.max().item()), "mean_rel": float(rel.mean().item()),
+                                  "rows_changed": int((t8 != t32).sum().item()), "rows": n4}
+    out["fp8_in_bound_frac"] = out["fp8"]["in_bound_unrefined_frac"]
+    out["bf16_speedup"] = out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"]
+    out["fp8_raw_speedup"] = out["fp32"]["ms_per_step"] / out["fp8"]["ms_per_step"]
+    del X4, c32, c8
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -213,6 +263,7 @@ def main():
         extra["low_rank_1024"] = lr
         del X3
         torch.cuda.empty_cache()
+        extra["heavy_tail_4096"] = heavy_tail_runs(max(2, args.steps // 8))
 
     base = None
     if not args.no_cpu_baseline:

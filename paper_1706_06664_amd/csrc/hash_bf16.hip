@@ -65,8 +65,9 @@ __device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)
 
 // Convert + row norms: X (FP32 [n][d]) -> Xh, Xl (bf16 bits [n][DP], zero-padded to
 // DP) and the row norms A = ||x_h||, B = ||x_l||, C = ||rho_x|| (FP32 sums of squares
-// rounded up by norm_up, square roots by 2^-20).  One wave per row; each lane takes 8
-// consecutive k per step so every store is 16 bytes.
+// rounded up by norm_up, square roots by 2^-20).  One wave per row; lane l takes the 4
+// consecutive k at 4l + 256i (a wave instruction reads 1 KB contiguous) and writes 8
+// bytes of hi and 8 of lo.
 template <bool VEC>
 __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ X, int64_t n, int d, int DP,
                                                            uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
@@ -77,22 +78,17 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
     if (row >= n) return;
     const float* xr = X + row * (int64_t)d;
     float sA = 0.f, sB = 0.f, sC = 0.f;
-    for (int k0 = 8 * lane; k0 < DP; k0 += 512) {
-        float v[8];
-        if (VEC && k0 + 8 <= d) {
-            const f4 a0 = *reinterpret_cast<const f4*>(xr + k0), a1 = *reinterpret_cast<const f4*>(xr + k0 + 4);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = a0[e];
-                v[4 + e] = a1[e];
-            }
+    for (int k0 = 4 * lane; k0 < DP; k0 += 256) {
+        f4 v;
+        if (VEC && k0 + 4 <= d) {
+            v = *reinterpret_cast<const f4*>(xr + k0);
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (k0 + e < d) ? xr[k0 + e] : 0.f;
+            for (int e = 0; e < 4; ++e) v[e] = (k0 + e < d) ? xr[k0 + e] : 0.f;
         }
-        s8v ph, pl;
+        s4v ph, pl;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 4; ++e) {
             const uint16_t hb = bf16_bits(v[e]);
             const float hv = bf16_val(hb);
             const float r1 = v[e] - hv;  // exact
@@ -105,8 +101,8 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
             ph[e] = (short)hb;
             pl[e] = (short)lb;
         }
-        *reinterpret_cast<s8v*>(Xh + row * (int64_t)DP + k0) = ph;
-        *reinterpret_cast<s8v*>(Xl + row * (int64_t)DP + k0) = pl;
+        *reinterpret_cast<s4v*>(Xh + row * (int64_t)DP + k0) = ph;
+        *reinterpret_cast<s4v*>(Xl + row * (int64_t)DP + k0) = pl;
     }
     for (int off = 32; off > 0; off >>= 1) {
         sA += __shfl_xor(sA, off, 64);

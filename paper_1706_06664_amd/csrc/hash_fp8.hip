@@ -64,8 +64,19 @@ __device__ inline uint32_t e4m3_encode(float v, float& q) {
     return s | (E << 3) | M;
 }
 
-// Convert + row norms: one wave per row.  Pass 1 finds max|x|; pass 2 scales by the
-// power of two, encodes, writes Xq [n][DP] bytes and A = ||x^||, B = ||dx||.
+// Convert + row norms: one wave per row.  Lane l takes the 4 consecutive k at
+// 4l + 256i (one 16-byte load; a wave instruction reads 1 KB contiguous).  Rows of up
+// to RCACHE*256 values stay in registers between the max pass and the encode pass.
+constexpr int RCACHE = 16;
+
+__device__ inline f4 load4(const float* xr, int k, int d, bool vec) {
+    if (vec && k + 4 <= d) return *reinterpret_cast<const f4*>(xr + k);
+    f4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (k + e < d) ? xr[k + e] : 0.f;
+    return v;
+}
+
 template <bool VEC>
 __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restrict__ X, int64_t n, int d, int DP,
                                                           uint8_t* __restrict__ Xq, float* __restrict__ rowA,
@@ -74,37 +85,48 @@ __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restric
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
     const float* xr = X + row * (int64_t)d;
+    f4 cache[RCACHE];
     float mx = 0.f;
-    for (int k = lane; k < d; k += 64) mx = fmaxf(mx, fabsf(xr[k]));
+#pragma unroll
+    for (int i = 0; i < RCACHE; ++i) {
+        cache[i] = f4{0.f, 0.f, 0.f, 0.f};
+        if (i * 256 < DP) {
+            cache[i] = load4(xr, 4 * lane + 256 * i, d, VEC);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(cache[i][0]), fabsf(cache[i][1])),
+                                 fmaxf(fabsf(cache[i][2]), fabsf(cache[i][3]))));
+        }
+    }
+    for (int k = 4 * lane + 256 * RCACHE; k < DP; k += 256) {
+        const f4 v = load4(xr, k, d, VEC);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+    }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    // scale exponent: smallest e with max|x| * 2^-e <= 448
+    // scale exponent: smallest e with max|x| * 2^-e <= 448; multiplying by 2^-e is exact
     int e = 0;
     if (mx > 0.f) {
         e = ilogbf(mx / 448.f);
-        if (ldexpf(mx, -e) > 448.f) ++e;
-        if (ldexpf(mx, -e) > 448.f) ++e;
+        while (ldexpf(mx, -e) > 448.f) ++e;
     }
+    const float sc = ldexpf(1.f, -e);
     float sA = 0.f, sB = 0.f;
-    for (int k0 = 16 * lane; k0 < DP; k0 += 1024) {
-        uint32_t w4[4];
+    auto encode = [&](f4 v, int k) {
+        uint32_t word = 0;
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int k = k0 + 4 * q4 + b;
-                const float x = (k < d) ? ldexpf(xr[k], -e) : 0.f;
-                float qv;
-                const uint32_t code = e4m3_encode(x, qv);
-                const float dx = x - qv;  // exact
-                sA = fmaf(qv, qv, sA);
-                sB = fmaf(dx, dx, sB);
-                word |= code << (8 * b);
-            }
-            w4[q4] = word;
+        for (int b = 0; b < 4; ++b) {
+            const float x = v[b] * sc;
+            float qv;
+            const uint32_t code = e4m3_encode(x, qv);
+            const float dx = x - qv;  // exact
+            sA = fmaf(qv, qv, sA);
+            sB = fmaf(dx, dx, sB);
+            word |= code << (8 * b);
         }
-        *reinterpret_cast<i4v*>(Xq + row * (int64_t)DP + k0) = i4v{(int)w4[0], (int)w4[1], (int)w4[2], (int)w4[3]};
-    }
+        *reinterpret_cast<uint32_t*>(Xq + row * (int64_t)DP + k) = word;
+    };
+#pragma unroll
+    for (int i = 0; i < RCACHE; ++i)
+        if (4 * lane + 256 * i < DP) encode(cache[i], 4 * lane + 256 * i);
+    for (int k = 4 * lane + 256 * RCACHE; k < DP; k += 256) encode(load4(xr, k, d, VEC), k);
     for (int off = 32; off > 0; off >>= 1) {
         sA += __shfl_xor(sA, off, 64);
         sB += __shfl_xor(sB, off, 64);
