@@ -208,3 +208,36 @@ def drifting_mixture_rows(rid: int, n: int, d: int, seed: int = 5, n_means: int 
     anom = rng.random(n) < anomaly_frac
     X[anom] = rng.uniform(-20.0, 20.0, size=(int(anom.sum()), d))
     return X.astype(np.float32), anom
+
+
+def serving_trace(n_requests: int, d: int, seed: int = 5, median_batch: int = 256, sigma_log: float = 1.0,
+                  max_batch: int = 65_536, rate_per_s: float = 1000.0, insert_frac: float = 0.7,
+                  pool_rows: int | None = None):
+    """Request log and host rows of the serving workload.
+
+    Returns (kind int32 [R] with 0 = insert and 1 = score, n int64 [R], row0 int64 [R],
+    out0 int64 [R], t_arrival float64 [R] in seconds, pool float32 [rows][d]).  Score
+    outputs are packed: request r writes [out0, out0 + n).  With pool_rows=None every
+    request has its own rows, drifting_mixture_rows(r, n), laid out in request order.
+    Otherwise the pool holds pool_rows drifting rows (blocks of 16,384 rows, block b drawn as
+    request id 1000*b) and request r reads the window starting at a seeded offset."""
+    reqs = serving_requests(n_requests, seed=seed, insert_frac=insert_frac, median_batch=median_batch,
+                            sigma_log=sigma_log, max_batch=max_batch, rate_per_s=rate_per_s)
+    kind = np.array([0 if q.kind == "insert" else 1 for q in reqs], np.int32)
+    n = np.array([q.n for q in reqs], np.int64)
+    t = np.array([q.arrival_s for q in reqs], np.float64)
+    out0 = np.zeros(n_requests, np.int64)
+    sc = kind == 1
+    out0[sc] = np.concatenate([[0], np.cumsum(n[sc])[:-1]]) if sc.any() else []
+    if pool_rows is None:
+        row0 = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+        pool = np.concatenate([drifting_mixture_rows(r, int(n[r]), d, seed=seed)[0] for r in range(n_requests)])
+    else:
+        blk = 16_384
+        nb = -(-pool_rows // blk)
+        pool = np.concatenate([drifting_mixture_rows(1000 * b, blk, d, seed=seed)[0] for b in range(nb)])[:pool_rows]
+        if n.max() > pool_rows:
+            raise ValueError("pool smaller than the largest request")
+        rng = np.random.Generator(np.random.PCG64([seed, 7]))
+        row0 = (rng.random(n_requests) * (pool_rows - n + 1)).astype(np.int64)
+    return kind, n, row0, out0, t, np.ascontiguousarray(pool, np.float32)

@@ -131,7 +131,8 @@ typedef struct {
  * device cannot be used.  *out is set only on success. */
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out);
 
-/* Synchronise the device and free everything the context owns.  NULL is a no-op. */
+/* Synchronise the device and free everything the context owns.  NULL is a no-op.
+ * ACE_E_STATE (nothing freed) while a serving loop is attached (ace_server_create). */
 ace_status ace_destroy(ace_ctx ctx);
 
 /* Zero the counts, the per-table sums and the scored set (stream-ordered). */
@@ -235,6 +236,96 @@ ace_status ace_debug_set_capacity(ace_ctx ctx, int64_t max_points);
 /* Lower the number of queued uncertain projections per chunk (0 restores the default), so
  * that the in-kernel path taken when the queue is full can be exercised. */
 ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
+
+/* ------------------------------------------------------------------------------------ */
+/* Serving loop: a request queue in front of one context (counting and query phases of
+ * Alg. 1 arriving as a stream of batches).
+ *
+ * Admission takes one of `slots` slots; each slot has its own HIP stream, hash workspace,
+ * device buffers of max_rows rows and pinned host staging.  A request runs, on its slot's
+ * stream: host-to-device copy of its rows, hash, then the count update (insert) or the
+ * score and a device-to-host copy of s and T (score).  A completion thread observes the
+ * slot's event, copies staged outputs to the caller's buffers and records the latency
+ * (from arrival to that observation).
+ *
+ * Ordering: the results equal those of running the requests one at a time in admission
+ * order.  A score sees exactly the inserts admitted before it; inserts overlap with each
+ * other, scores overlap with each other, and a request waits only on in-flight requests of
+ * the other kind.  Scored rows join the context's scored set (as ace_score).
+ *
+ * While a server is attached, the context must not be used directly except after
+ * ace_server_drain returned and before the next submit, from the submitting thread;
+ * ace_destroy of the context returns ACE_E_STATE until ace_server_destroy. */
+typedef struct ace_server_s* ace_server;
+
+typedef enum { ACE_REQ_INSERT = 0, ACE_REQ_SCORE = 1 } ace_req_kind;
+
+/* Flag of ace_server_submit / ace_server_replay: the host rows (and, for scores, the host
+ * outputs) are pinned memory (hipHostMalloc) that stays valid and unchanged until the
+ * request completes; the copies then read and write them directly.  Without it the rows
+ * are copied into the slot's staging before submit returns, and outputs are copied out by
+ * the completion thread. */
+#define ACE_SUBMIT_PINNED 1
+
+typedef struct {
+    int32_t slots;       /* 1..64 concurrent requests */
+    int32_t use_graphs;  /* must be 0 */
+    int64_t max_rows;    /* rows per request, 1..2^24 */
+    int64_t reserved;    /* must be 0 */
+} ace_server_config;
+
+typedef struct {
+    int32_t kind;         /* ace_req_kind */
+    int32_t pad;
+    int64_t n;            /* rows, 1..max_rows */
+    int64_t row0;         /* first row in the pool */
+    int64_t out0;         /* score requests: first output element in s_out / T_out */
+    double t_arrival_s;   /* arrival time after the start of the replay; 0 = as soon as admitted */
+} ace_request;
+
+typedef struct {
+    int64_t requests, inserts, scores;   /* completed since the last reset */
+    int64_t rows, insert_rows;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency, arrival to completion */
+    double p99_insert_ms, p99_score_ms;
+    double wall_ms;                      /* first arrival to last completion */
+} ace_server_stats;
+
+/* Create a server owning ctx's request stream.  ACE_E_INVALID on a bad config,
+ * ACE_E_STATE if ctx already has a server, ACE_E_NOMEM if the slots do not fit. */
+ace_status ace_server_create(ace_ctx ctx, const ace_server_config* cfg, ace_server* out);
+
+/* Admit one request (blocks while every slot is busy).  X_host: FP32 [n][d] host rows.
+ * Scores: s_host (FP32 [n]) and T_host (uint32 [n]) may each be NULL; they are filled when
+ * the request completes.  *ticket (may be NULL) identifies it for ace_server_wait.
+ * ACE_E_INVALID for n outside 1..max_rows or a bad kind/flag; ACE_E_OVERFLOW as for
+ * ace_insert / ace_score; a device error is sticky on the context and on the server. */
+ace_status ace_server_submit(ace_server srv, int32_t kind, const float* X_host, int64_t n, float* s_host,
+                             uint32_t* T_host, int32_t flags, uint64_t* ticket);
+
+/* Wait until the request completed; *latency_ms (may be NULL) receives its latency. */
+ace_status ace_server_wait(ace_server srv, uint64_t ticket, double* latency_ms);
+
+/* Wait until every admitted request completed. */
+ace_status ace_server_drain(ace_server srv);
+
+/* Trace-driven load: admit reqs[0..nreq) in order, each at its arrival time (open loop:
+ * latency counts from the scheduled arrival, so admission delays are included), with rows
+ * pool[row0 .. row0+n) of the host pool FP32 [pool_rows][d].  Scores write s_out/T_out at
+ * out0 (either may be NULL).  Waits for all of them; latency_ms[nreq] (may be NULL)
+ * receives each request's latency. */
+ace_status ace_server_replay(ace_server srv, const ace_request* reqs, int64_t nreq, const float* pool,
+                             int64_t pool_rows, int32_t flags, float* s_out, uint32_t* T_out, double* latency_ms);
+
+/* Latency and throughput of the requests completed since the last reset (nearest-rank
+ * percentiles). */
+ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out);
+
+/* Drain, then forget the recorded latencies. */
+ace_status ace_server_reset_stats(ace_server srv);
+
+/* Drain and free the slots; the context stays valid. */
+ace_status ace_server_destroy(ace_server srv);
 
 #ifdef __cplusplus
 }

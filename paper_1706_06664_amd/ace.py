@@ -29,7 +29,17 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_threshold", "ace_flag", "ace_hash", "ace_insert_codes", "ace_score_codes", "ace_get_counts",
            "ace_get_table_stats", "ace_get_counters", "ace_set_counts", "ace_status_string", "ace_version",
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
-           "ace_debug_set_refine_queue"]
+           "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
+           "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
+           "ace_server_destroy"]
+
+REQ_INSERT, REQ_SCORE = 0, 1
+SUBMIT_PINNED = 1
+_KINDS = {"insert": REQ_INSERT, "score": REQ_SCORE}
+
+# Layout of ace_request (one record per request of a replayed trace).
+REQUEST_DTYPE = np.dtype([("kind", "<i4"), ("pad", "<i4"), ("n", "<i8"), ("row0", "<i8"), ("out0", "<i8"),
+                          ("t_arrival_s", "<f8")])
 
 
 class AceError(RuntimeError):
@@ -67,6 +77,18 @@ class Counters(ctypes.Structure):
                 ("bits_in_bound_unrefined", ctypes.c_uint64)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("max_rows", ctypes.c_int64),
+                ("reserved", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("inserts", ctypes.c_int64), ("scores", ctypes.c_int64),
+                ("rows", ctypes.c_int64), ("insert_rows", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("p99_insert_ms", ctypes.c_double), ("p99_score_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -101,6 +123,14 @@ def load_library(path: str = LIB_PATH):
         "ace_profile_enable": [P, i32],
         "ace_debug_set_refine_queue": [P, i64],
         "ace_get_profile": [P, ctypes.POINTER(Profile)],
+        "ace_server_create": [P, ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
+        "ace_server_submit": [P, i32, P, i64, P, P, i32, ctypes.POINTER(ctypes.c_uint64)],
+        "ace_server_wait": [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
+        "ace_server_drain": [P],
+        "ace_server_replay": [P, P, i64, P, i64, i32, P, P, P],
+        "ace_server_get_stats": [P, ctypes.POINTER(ServerStats)],
+        "ace_server_reset_stats": [P],
+        "ace_server_destroy": [P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -156,9 +186,16 @@ class ACE:
         self.h = h
 
     def close(self):
+        srv = getattr(self, "_server", None)
+        if srv is not None:
+            srv.close()
         if getattr(self, "h", None):
-            self.lib.ace_destroy(self.h)
+            _check(self.lib.ace_destroy(self.h), "ace_destroy")
             self.h = None
+
+    def server(self, slots: int = 4, max_rows: int = 65536) -> "Server":
+        """Attach a serving loop (request queue with `slots` concurrent requests)."""
+        return Server(self, slots, max_rows)
 
     def __del__(self):
         try:
@@ -267,6 +304,92 @@ class ACE:
     def set_counts(self, counts: np.ndarray, n: int):
         counts = np.ascontiguousarray(counts, np.int32)
         _check(self.lib.ace_set_counts(self.h, counts.ctypes.data_as(ctypes.c_void_p), int(n)), "ace_set_counts")
+
+
+def _host_ptr(a, dtype, what: str):
+    """Address of a host buffer: a C-contiguous numpy array or a CPU torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"{what} must be a C-contiguous {np.dtype(dtype)} array")
+        return a.ctypes.data
+    if a.device.type != "cpu" or not a.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous CPU tensor")
+    return a.data_ptr()
+
+
+class Server:
+    """Serving loop of one ACE context: requests are admitted in order onto `slots`
+    streams; a score sees exactly the inserts admitted before it."""
+
+    def __init__(self, ace: ACE, slots: int = 4, max_rows: int = 65536):
+        if getattr(ace, "_server", None) is not None:
+            raise AceError(6, "ace_server_create")
+        self.ace, self.lib, self.d = ace, ace.lib, ace.d
+        cfg = ServerConfig(int(slots), 0, int(max_rows), 0)
+        h = ctypes.c_void_p()
+        _check(self.lib.ace_server_create(ace.h, ctypes.byref(cfg), ctypes.byref(h)), "ace_server_create")
+        self.h = h
+        self._keep = {}
+        ace._server = self
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self.lib.ace_server_destroy(self.h), "ace_server_destroy")
+            self.h = None
+            self._keep.clear()
+            self.ace._server = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, kind, X, s=None, T=None, pinned: bool = False) -> int:
+        """Admit one request.  X: host float32 [n][d].  For scores, s (float32 [n]) and T
+        (uint32 [n]) are host buffers filled when the request completes (keep them until
+        wait/drain).  pinned=True: X, s and T are pinned and stay untouched until then."""
+        k = _KINDS[kind] if isinstance(kind, str) else int(kind)
+        n = int(X.shape[0])
+        if X.shape[1] != self.d:
+            raise ValueError(f"X must be [n][{self.d}]")
+        t = ctypes.c_uint64()
+        _check(self.lib.ace_server_submit(self.h, k, _host_ptr(X, np.float32, "X"), n,
+                                          _host_ptr(s, np.float32, "s"), _host_ptr(T, np.uint32, "T"),
+                                          SUBMIT_PINNED if pinned else 0, ctypes.byref(t)), "ace_server_submit")
+        self._keep[t.value] = (X, s, T)
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(self.lib.ace_server_wait(self.h, int(ticket), ctypes.byref(lat)), "ace_server_wait")
+        self._keep.pop(int(ticket), None)
+        return lat.value
+
+    def drain(self):
+        _check(self.lib.ace_server_drain(self.h), "ace_server_drain")
+        self._keep.clear()
+
+    def replay(self, reqs: np.ndarray, pool, s_out=None, T_out=None, pinned: bool = False) -> np.ndarray:
+        """Replay a trace (REQUEST_DTYPE records) against host rows `pool` [rows][d];
+        returns each request's latency in ms."""
+        reqs = np.ascontiguousarray(reqs, REQUEST_DTYPE)
+        lat = np.empty(len(reqs), np.float64)
+        _check(self.lib.ace_server_replay(self.h, reqs.ctypes.data, len(reqs), _host_ptr(pool, np.float32, "pool"),
+                                          int(pool.shape[0]), SUBMIT_PINNED if pinned else 0,
+                                          _host_ptr(s_out, np.float32, "s_out"), _host_ptr(T_out, np.uint32, "T_out"),
+                                          lat.ctypes.data), "ace_server_replay")
+        return lat
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        _check(self.lib.ace_server_get_stats(self.h, ctypes.byref(out)), "ace_server_get_stats")
+        return {f: getattr(out, f) for f, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _check(self.lib.ace_server_reset_stats(self.h), "ace_server_reset_stats")
 
 
 def codes_as_uint16(codes_t) -> np.ndarray:

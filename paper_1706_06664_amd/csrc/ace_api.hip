@@ -7,55 +7,61 @@
 #include <new>
 #include <vector>
 
-#include "ace_internal.h"
+#include "ace_context.h"
 
 using namespace ace;
 
-struct ace_ctx_s {
-    ace_config cfg;
-    int TW = 5;            // tables per wave in the projection kernel
-    int n_tiles_n = 1;     // column tiles
-    int NP = 0;            // padded columns allocated (n_tiles_n * 32 * TW)
-    int DP = 0;            // padded contraction length
-    float gx = 0.f, eps_abs = 0.f;
+namespace ace {
 
-    float* Wt = nullptr;   // [NP][DP]
-    float* wb = nullptr;   // [NP]
-    uint8_t* Wq = nullptr;   // [NP][DP] e4m3 codes of the scaled columns (FP8 precision)
-    uint8_t* ws_xq = nullptr;  // [ws_rows][DP] e4m3 rows (FP8 precision)
-    uint16_t* Wh = nullptr;  // [NP][DP] split-BF16 hi / lo (BF16 precision)
-    uint16_t* Wl = nullptr;
-    float* wbA = nullptr;    // [4][NP] BF16 bound factors (A, B, C, absolute)
-    int32_t* counts = nullptr;   // [L][2^K]
-    u64* S2 = nullptr;           // [L]
-    u64* S3 = nullptr;           // [L][2]
-    u64* mom = nullptr;          // m, sum T, sum T^2 lo, hi
-    u64* rcnt = nullptr;         // bits refined, bits flipped
-    unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
-    DevThresh* thr = nullptr;
-    uint16_t* ws_codes = nullptr;  // [L][ws_rows] (+ padding for 32-bit patch atomics)
-    uint16_t* ws_refined = nullptr;  // same shape, allocated on first request
-    int64_t ws_rows = 0;
-    uint16_t* ws_xh = nullptr;     // [ws_rows][DP] split-BF16 rows (BF16 precision)
-    uint16_t* ws_xl = nullptr;
-    float* ws_rown = nullptr;      // [3][ws_rows] row norms
-    u64* list = nullptr;           // queue of uncertain projections
-    u64* list_count = nullptr;
-    u64 list_alloc = 0, list_cap = 0;
+ace_status dev_alloc(ace_ctx c, void** p, size_t bytes) {
+    if (c->cfg.mem_budget > 0 && c->bytes + bytes > (size_t)c->cfg.mem_budget) return ACE_E_NOMEM;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return ACE_E_NOMEM;
+    }
+    c->bytes += bytes;
+    return ACE_OK;
+}
 
-    int64_t n_total = 0;
-    int64_t cap = INT32_MAX;
-    u64 bits_hashed = 0;
-    size_t bytes = 0;
-    ace_status sticky = ACE_OK;
-    int fail_next = 0;
+// Record a launch result: a failed launch makes the context sticky.
+ace_status check(ace_ctx c, hipError_t e) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->sticky = ACE_E_DEVICE;
+        return ACE_E_DEVICE;
+    }
+    return ACE_OK;
+}
 
-    // Event timing: pairs of (start, end, class) recorded while profiling is on.
-    int profiling = 0;
-    struct Timed { hipEvent_t a, b; int cls; int64_t rows; };
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> pool;
-};
+void ws_free(Workspace* w) {
+    void* ptrs[] = {w->codes, w->refined, w->list, w->list_count, w->xh, w->xl, w->xq, w->rown};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    *w = Workspace();
+}
+
+ace_status ws_alloc(ace_ctx c, Workspace* w, int64_t rows) {
+    const size_t L = (size_t)c->cfg.L;
+    w->rows = rows;
+    ace_status st = dev_alloc(c, (void**)&w->codes, sizeof(uint16_t) * (L * rows + 2));
+    // Queue for projections inside the bound: 1/32 of a chunk's bits (a full queue only
+    // slows the epilogue down, it never changes a result).
+    w->list_alloc = (u64)rows * (u64)L * KPAD / 32;
+    if (w->list_alloc < 65536) w->list_alloc = 65536;
+    st = st ? st : dev_alloc(c, (void**)&w->list, sizeof(u64) * (size_t)w->list_alloc);
+    st = st ? st : dev_alloc(c, (void**)&w->list_count, sizeof(u64));
+    if (c->cfg.precision == ACE_BF16) {
+        st = st ? st : dev_alloc(c, (void**)&w->xh, sizeof(uint16_t) * (size_t)rows * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&w->xl, sizeof(uint16_t) * (size_t)rows * c->DP);
+    }
+    if (c->cfg.precision == ACE_FP8E4M3) st = st ? st : dev_alloc(c, (void**)&w->xq, (size_t)rows * c->DP);
+    if (c->cfg.precision != ACE_FP32) st = st ? st : dev_alloc(c, (void**)&w->rown, sizeof(float) * 3 * (size_t)rows);
+    if (st) ws_free(w);
+    return st;
+}
+
+}  // namespace ace
 
 namespace {
 
@@ -70,17 +76,6 @@ struct DeviceGuard {
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
-
-ace_status dev_alloc(ace_ctx c, void** p, size_t bytes) {
-    if (c->cfg.mem_budget > 0 && c->bytes + bytes > (size_t)c->cfg.mem_budget) return ACE_E_NOMEM;
-    if (hipMalloc(p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return ACE_E_NOMEM;
-    }
-    c->bytes += bytes;
-    return ACE_OK;
-}
 
 enum { CLS_HASH = 0, CLS_UPDATE = 1, CLS_SCORE = 2, CLS_OTHER = 3, CLS_REFINE = 4, CLS_CONVERT = 5 };
 
@@ -128,20 +123,10 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->ws_xq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr, c->ws_codes,
-                    c->ws_refined, c->list, c->list_count, c->ws_xh, c->ws_xl, c->ws_rown};
+    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr};
+    ws_free(&c->ws);
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-}
-
-// Record a launch result: a failed launch makes the context sticky.
-ace_status check(ace_ctx c, hipError_t e) {
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        c->sticky = ACE_E_DEVICE;
-        return ACE_E_DEVICE;
-    }
-    return ACE_OK;
 }
 
 ace_status enter(ace_ctx c) {
@@ -214,13 +199,15 @@ int pick_tw(int L, bool fp32) {
     return best;
 }
 
-// Hash rows [0, n) of X (one chunk of at most ws_rows rows) into the workspace codes
+}  // namespace
+
+// Hash rows [0, n) of X (one chunk of at most w->rows rows) into the workspace codes
 // [L][n]: projection + sign-pack, then the FP64 pass over the queued projections.
-ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, hipStream_t s) {
-    ace_status st = check(c, launch_zero(c->list_count, sizeof(u64), s));
+ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s) {
+    ace_status st = check(c, launch_zero(w->list_count, sizeof(u64), s));
     if (st) return st;
     if (want_refined) {
-        st = check(c, launch_zero(c->ws_refined, sizeof(uint16_t) * ((size_t)c->cfg.L * n + 2), s));
+        st = check(c, launch_zero(w->refined, sizeof(uint16_t) * ((size_t)c->cfg.L * n + 2), s));
         if (st) return st;
     }
     HashArgs a;
@@ -237,11 +224,11 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     a.gx = c->gx;
     a.eps_abs = c->eps_abs;
     a.refine = c->cfg.refine;
-    a.codes = c->ws_codes;
+    a.codes = w->codes;
     a.ldc = n;
-    a.list = c->list;
-    a.list_count = c->list_count;
-    a.list_cap = c->list_cap;
+    a.list = w->list;
+    a.list_count = w->list_count;
+    a.list_cap = c->list_cap < w->list_alloc ? c->list_cap : w->list_alloc;
     a.counters = c->rcnt;
     a.Wh = c->Wh;
     a.Wl = c->Wl;
@@ -255,28 +242,28 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     if (c->cfg.precision == ACE_FP8E4M3) {
         {
             Bracket br(c, s, CLS_CONVERT, n);
-            st = check(c, launch_convert_fp8(X, n, c->cfg.d, c->DP, vec, c->ws_xq, c->ws_rown, c->ws_rown + c->ws_rows,
+            st = check(c, launch_convert_fp8(X, n, c->cfg.d, c->DP, vec, w->xq, w->rown, w->rown + w->rows,
                                              a.norm_up, s));
         }
         if (st) return st;
-        a.Xq = c->ws_xq;
+        a.Xq = w->xq;
         a.Wq = c->Wq;
-        a.rowA = c->ws_rown;
-        a.rowB = c->ws_rown + c->ws_rows;
+        a.rowA = w->rown;
+        a.rowB = w->rown + w->rows;
         Bracket br(c, s, CLS_HASH, n);
         st = check(c, launch_hash_fp8(a, c->TW, s));
     } else if (c->cfg.precision == ACE_BF16) {
         {
             Bracket br(c, s, CLS_CONVERT, n);
-            st = check(c, launch_convert_bf16(X, n, c->cfg.d, c->DP, vec, c->ws_xh, c->ws_xl, c->ws_rown,
-                                              c->ws_rown + c->ws_rows, c->ws_rown + 2 * c->ws_rows, a.norm_up, s));
+            st = check(c, launch_convert_bf16(X, n, c->cfg.d, c->DP, vec, w->xh, w->xl, w->rown,
+                                              w->rown + w->rows, w->rown + 2 * w->rows, a.norm_up, s));
         }
         if (st) return st;
-        a.Xh = c->ws_xh;
-        a.Xl = c->ws_xl;
-        a.rowA = c->ws_rown;
-        a.rowB = c->ws_rown + c->ws_rows;
-        a.rowC = c->ws_rown + 2 * c->ws_rows;
+        a.Xh = w->xh;
+        a.Xl = w->xl;
+        a.rowA = w->rown;
+        a.rowB = w->rown + w->rows;
+        a.rowC = w->rown + 2 * w->rows;
         Bracket br(c, s, CLS_HASH, n);
         st = check(c, launch_hash_bf16(a, c->TW, s));
     } else {
@@ -291,25 +278,27 @@ ace_status hash_chunk(ace_ctx c, const float* X, int64_t n, bool want_refined, h
     r.DP = c->DP;
     r.L = c->cfg.L;
     r.K = c->cfg.K;
-    r.codes = c->ws_codes;
+    r.codes = w->codes;
     r.ldc = n;
-    r.refined = want_refined ? c->ws_refined : nullptr;
-    r.list = c->list;
-    r.list_count = c->list_count;
-    r.list_cap = c->list_cap;
+    r.refined = want_refined ? w->refined : nullptr;
+    r.list = w->list;
+    r.list_count = w->list_count;
+    r.list_cap = a.list_cap;
     r.counters = c->rcnt;
     Bracket br(c, s, CLS_REFINE, n);
-    return check(c, launch_refine(r, (int64_t)c->list_cap, vec, s));
+    return check(c, launch_refine(r, (int64_t)a.list_cap, vec, s));
 }
+
+namespace {
 
 ace_status update_rows(ace_ctx c, const float* X, int64_t n, int sign, hipStream_t s) {
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        ace_status st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, false, s);
+        ace_status st = hash_chunk(c, &c->ws, X + r0 * (int64_t)c->cfg.d, m, false, s);
         if (st != ACE_OK) return st;
         {
             Bracket br(c, s, CLS_UPDATE, m);
-            st = check(c, launch_count_update(c->ws_codes, m, m, c->cfg.K, c->cfg.L, sign, c->counts, c->S2, c->S3,
+            st = check(c, launch_count_update(c->ws.codes, m, m, c->cfg.K, c->cfg.L, sign, c->counts, c->S2, c->S3,
                                               c->err, s));
         }
         if (st != ACE_OK) return st;
@@ -392,16 +381,11 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     if (cfg->precision == ACE_FP8E4M3) {
         st = st ? st : dev_alloc(c, (void**)&c->Wq, (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
-        st = st ? st : dev_alloc(c, (void**)&c->ws_xq, (size_t)c->ws_rows * c->DP);
-        st = st ? st : dev_alloc(c, (void**)&c->ws_rown, sizeof(float) * 3 * (size_t)c->ws_rows);
     }
     if (cfg->precision == ACE_BF16) {
         st = st ? st : dev_alloc(c, (void**)&c->Wh, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->Wl, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
-        st = st ? st : dev_alloc(c, (void**)&c->ws_xh, sizeof(uint16_t) * (size_t)c->ws_rows * c->DP);
-        st = st ? st : dev_alloc(c, (void**)&c->ws_xl, sizeof(uint16_t) * (size_t)c->ws_rows * c->DP);
-        st = st ? st : dev_alloc(c, (void**)&c->ws_rown, sizeof(float) * 3 * (size_t)c->ws_rows);
     }
     st = st ? st : dev_alloc(c, (void**)&c->counts, sizeof(int32_t) * (size_t)L * B);
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
@@ -410,14 +394,8 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
-    st = st ? st : dev_alloc(c, (void**)&c->ws_codes, sizeof(uint16_t) * ((size_t)L * c->ws_rows + 2));
-    // Queue for projections inside the FP32 bound: 1/32 of a chunk's bits (a full queue
-    // only slows the epilogue down, it never changes a result).
-    c->list_alloc = (u64)c->ws_rows * (u64)L * KPAD / 32;
-    if (c->list_alloc < 65536) c->list_alloc = 65536;
-    c->list_cap = c->list_alloc;
-    st = st ? st : dev_alloc(c, (void**)&c->list, sizeof(u64) * (size_t)c->list_alloc);
-    st = st ? st : dev_alloc(c, (void**)&c->list_count, sizeof(u64));
+    st = st ? st : ws_alloc(c, &c->ws, c->ws_rows);
+    c->list_cap = c->ws.list_alloc;
     if (st != ACE_OK) {
         free_all(c);
         delete c;
@@ -540,6 +518,7 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
 
 ace_status ace_destroy(ace_ctx c) {
     if (!c) return ACE_OK;
+    if (c->server_attached) return ACE_E_STATE;
     DeviceGuard g(c->cfg.device);
     (void)hipDeviceSynchronize();
     free_all(c);
@@ -628,11 +607,11 @@ ace_status ace_score(ace_ctx c, const float* X, int64_t n, float* s_out, uint32_
     hipStream_t s = (hipStream_t)stream;
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, false, s);
+        st = hash_chunk(c, &c->ws, X + r0 * (int64_t)c->cfg.d, m, false, s);
         if (st) return st;
         {
             Bracket br(c, s, CLS_SCORE, m);
-            st = check(c, launch_score(c->ws_codes, m, m, c->cfg.K, c->cfg.L, c->counts, s_out ? s_out + r0 : nullptr,
+            st = check(c, launch_score(c->ws.codes, m, m, c->cfg.K, c->cfg.L, c->counts, s_out ? s_out + r0 : nullptr,
                                        T_out ? T_out + r0 : nullptr, c->mom, s));
         }
         if (st) return st;
@@ -659,8 +638,8 @@ ace_status ace_hash(ace_ctx c, const float* X, int64_t n, uint16_t* codes, uint1
     if (n < 0 || (n > 0 && (!X || !codes))) return ACE_E_INVALID;
     if (n == 0) return ACE_OK;
     DeviceGuard g(c->cfg.device);
-    if (refined && !c->ws_refined) {
-        st = dev_alloc(c, (void**)&c->ws_refined, sizeof(uint16_t) * ((size_t)c->cfg.L * c->ws_rows + 2));
+    if (refined && !c->ws.refined) {
+        st = dev_alloc(c, (void**)&c->ws.refined, sizeof(uint16_t) * ((size_t)c->cfg.L * c->ws_rows + 2));
         if (st) return st;
     }
     if (take_injected_failure(c)) return ACE_E_DEVICE;
@@ -668,13 +647,13 @@ ace_status ace_hash(ace_ctx c, const float* X, int64_t n, uint16_t* codes, uint1
     const size_t L = (size_t)c->cfg.L;
     for (int64_t r0 = 0; r0 < n; r0 += c->ws_rows) {
         const int64_t m = (n - r0 < c->ws_rows) ? n - r0 : c->ws_rows;
-        st = hash_chunk(c, X + r0 * (int64_t)c->cfg.d, m, refined != nullptr, s);
+        st = hash_chunk(c, &c->ws, X + r0 * (int64_t)c->cfg.d, m, refined != nullptr, s);
         if (st) return st;
         // Workspace [L][m] -> caller's [L][n] at column r0.
-        st = check(c, hipMemcpy2DAsync(codes + r0, sizeof(uint16_t) * n, c->ws_codes, sizeof(uint16_t) * m,
+        st = check(c, hipMemcpy2DAsync(codes + r0, sizeof(uint16_t) * n, c->ws.codes, sizeof(uint16_t) * m,
                                        sizeof(uint16_t) * m, L, hipMemcpyDeviceToDevice, s));
         if (!st && refined)
-            st = check(c, hipMemcpy2DAsync(refined + r0, sizeof(uint16_t) * n, c->ws_refined, sizeof(uint16_t) * m,
+            st = check(c, hipMemcpy2DAsync(refined + r0, sizeof(uint16_t) * n, c->ws.refined, sizeof(uint16_t) * m,
                                            sizeof(uint16_t) * m, L, hipMemcpyDeviceToDevice, s));
         if (st) return st;
     }
@@ -846,7 +825,7 @@ ace_status ace_debug_fail_next(ace_ctx c) {
 
 ace_status ace_debug_set_refine_queue(ace_ctx c, int64_t entries) {
     if (!c || entries < 0) return ACE_E_INVALID;
-    c->list_cap = (entries == 0 || (u64)entries > c->list_alloc) ? c->list_alloc : (u64)entries;
+    c->list_cap = (entries == 0 || (u64)entries > c->ws.list_alloc) ? c->ws.list_alloc : (u64)entries;
     return ACE_OK;
 }
 

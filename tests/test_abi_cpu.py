@@ -73,3 +73,32 @@ def test_binding_fails_loudly_without_library(tmp_path):
             m.load_library(str(tmp_path / "missing.so"))
     finally:
         m._lib = saved
+
+
+def test_server_calls_reject_null_handles():
+    lib = _lib()
+    from paper_1706_06664_amd.ace import ServerConfig, ServerStats
+    h = ctypes.c_void_p()
+    cfg = ServerConfig(2, 0, 16, 0)
+    assert lib.ace_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert h.value is None
+    X = np.zeros((4, 8), np.float32)
+    t = ctypes.c_uint64()
+    assert lib.ace_server_submit(None, 0, X.ctypes.data, 4, None, None, 0, ctypes.byref(t)) == 1
+    assert lib.ace_server_wait(None, 0, None) == 1
+    assert lib.ace_server_drain(None) == 1
+    assert lib.ace_server_replay(None, None, 0, None, 0, 0, None, None, None) == 1
+    st = ServerStats()
+    assert lib.ace_server_get_stats(None, ctypes.byref(st)) == 1
+    assert lib.ace_server_reset_stats(None) == 1
+    assert lib.ace_server_destroy(None) == 1
+
+
+def test_request_record_layout_matches_header():
+    from paper_1706_06664_amd import REQUEST_DTYPE
+    from paper_1706_06664_amd.ace import ServerConfig, ServerStats
+    assert REQUEST_DTYPE.itemsize == 40
+    assert [REQUEST_DTYPE.fields[f][1] for f in ("kind", "pad", "n", "row0", "out0", "t_arrival_s")] == \
+        [0, 4, 8, 16, 24, 32]
+    assert ctypes.sizeof(ServerConfig) == 24
+    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8
