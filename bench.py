@@ -11,7 +11,10 @@ Headline workload (the `value`): connection-log shaped points, 494,021 x 120
 K = 15 bits, L = 50 tables, FP32 projections refined in FP64 inside the FP32
 error bound.  Further fields: the same workload in split-BF16 mode, and a dense
 4,000,000 x 1024 low-rank workload (K = 15, L = 64) in FP32 and split-BF16 mode
-with refined fractions, raw flip rates and raw score errors.
+with refined fractions, raw flip rates and raw score errors, a heavy-tailed
+1,000,000 x 4096 workload (K = 16, L = 100) in FP32, split-BF16 and FP8, and the
+serving loop (d = 256, K = 15, L = 50): saturation rate and p50/p99 latency at
+fixed offered loads.
 
 Prints one JSON line.
 """
@@ -197,6 +200,68 @@ def heavy_tail_runs(steps):
     return out
 
 
+def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536):
+    """Serving workload: d = 256, K = 15, L = 50.  A request log of n_req requests (70%
+    inserts, 30% scores; lognormal sizes, median 256 rows, sigma 1, at most 65,536 rows)
+    replayed against a 262,144-row pinned pool of drifting-mixture rows through the serving
+    loop.  Closed loop (every request queued at once) gives the saturation rate in FP32 and
+    BF16; open loop (Poisson arrivals at 0.5, 0.8 and 0.95 of the BF16 saturation request
+    rate) gives latency percentiles, from arrival to completion (host copies included)."""
+    import numpy as np
+    import torch
+    from ace_inputs import projection_matrix, serving_trace
+    from paper_1706_06664_amd import ACE, REQUEST_DTYPE
+    K, L, d = 15, 50, 256
+    kind, n, row0, out0, t, pool = serving_trace(n_req, d, seed=5, pool_rows=262_144)
+    W = projection_matrix(d, K, L, 1706066645)
+    poolp = torch.from_numpy(pool).pin_memory()
+    m = int(n[kind == 1].sum())
+    s_out = torch.zeros(m, dtype=torch.float32).pin_memory()
+    T_out = torch.zeros(m, dtype=torch.int32).pin_memory()
+    rec = np.zeros(n_req, REQUEST_DTYPE)
+    rec["kind"], rec["n"], rec["row0"], rec["out0"] = kind, n, row0, out0
+
+    def run(prec, arr=None):
+        ace = ACE(W, K, L, precision=prec)
+        srv = ace.server(slots=slots, max_rows=65_536, gather_max_bytes=gather_max_bytes, batch_rows=batch_rows)
+        srv.replay(rec[:500], poolp, s_out, T_out, pinned=True)   # warm-up
+        srv.reset_stats()
+        r = rec.copy()
+        if arr is not None:
+            r["t_arrival_s"] = arr
+        srv.replay(r, poolp, s_out, T_out, pinned=True)
+        st = srv.stats()
+        srv.close()
+        ace.close()
+        wall = st["wall_ms"] / 1e3
+        return {"points_per_s": st["rows"] / wall, "requests_per_s": st["requests"] / wall,
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "p99_queue_ms": st["p99_queue_ms"],
+                "max_ms": st["max_ms"], "batches": st["batches"],
+                "mean_batch_requests": st["mean_batch_requests"]}
+
+    out = {"workload": f"serving d={d}, K={K}, L={L}: {n_req} requests, {int(n.sum())} rows, 70% inserts, "
+                       f"lognormal sizes (median 256, sigma 1)",
+           "server": {"slots": slots, "batch_rows": batch_rows, "gather_max_bytes": gather_max_bytes,
+                      "max_rows": 65_536}}
+    for prec in ("fp32", "bf16"):
+        log(f"serving closed loop {prec}")
+        out[f"closed_loop_{prec}"] = run(prec)
+        log(f"  {out[f'closed_loop_{prec}']['points_per_s']:.3e} points/s")
+    sat = out["closed_loop_bf16"]["requests_per_s"]
+    out["open_loop_bf16"] = []
+    base_rate = n_req / t[-1]
+    for load in (0.5, 0.8, 0.95):
+        log(f"serving open loop bf16 at {load} of saturation")
+        o = run("bf16", arr=t * (base_rate / (load * sat)))
+        o["load"] = load
+        o["offered_requests_per_s"] = load * sat
+        out["open_loop_bf16"].append(o)
+        log(f"  p50 {o['p50_ms']:.3f} ms, p99 {o['p99_ms']:.3f} ms")
+    out["bf16_vs_fp32_closed_loop"] = out["closed_loop_bf16"]["points_per_s"] / out["closed_loop_fp32"]["points_per_s"]
+    out["pcie_bound_points_per_s"] = 55e9 / (4 * d)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +329,7 @@ def main():
         del X3
         torch.cuda.empty_cache()
         extra["heavy_tail_4096"] = heavy_tail_runs(max(2, args.steps // 8))
+        extra["serving_256"] = serving_runs()
 
     base = None
     if not args.no_cpu_baseline:

@@ -239,19 +239,22 @@ ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
 
 /* ------------------------------------------------------------------------------------ */
 /* Serving loop: a request queue in front of one context (counting and query phases of
- * Alg. 1 arriving as a stream of batches).
+ * Alg. 1 arriving as a stream of row blocks).
  *
- * Admission takes one of `slots` slots; each slot has its own HIP stream, hash workspace,
- * device buffers of max_rows rows and pinned host staging.  A request runs, on its slot's
- * stream: host-to-device copy of its rows, hash, then the count update (insert) or the
- * score and a device-to-host copy of s and T (score).  A completion thread observes the
- * slot's event, copies staged outputs to the caller's buffers and records the latency
- * (from arrival to that observation).
+ * Submission appends a request to a FIFO queue and returns.  A dispatcher thread batches
+ * continuously: whenever one of `slots` slots is free, the longest prefix of the queue that
+ * fits batch_rows rows (inserts and scores mixed; at least one request) becomes one batch.  Each slot has its own
+ * HIP stream, hash workspace, device buffers of max_rows rows and pinned host staging.  A
+ * batch runs, on its slot's stream: host-to-device copies of its rows, one hash of all of
+ * them, then its count phase (a count update per run of consecutive inserts, a score per
+ * run of consecutive scores) and a device-to-host copy of s and T.  A completion thread
+ * observes the slot's event, copies each request's outputs to the caller's buffers and
+ * records its latency (from arrival to that observation).
  *
  * Ordering: the results equal those of running the requests one at a time in admission
- * order.  A score sees exactly the inserts admitted before it; inserts overlap with each
- * other, scores overlap with each other, and a request waits only on in-flight requests of
- * the other kind.  Scored rows join the context's scored set (as ace_score).
+ * order.  Hashes of different batches overlap; count phases run in admission order (each
+ * waits on the previous batch's), so a score sees exactly the inserts admitted before it.
+ * Scored rows join the context's scored set (as ace_score).
  *
  * While a server is attached, the context must not be used directly except after
  * ace_server_drain returned and before the next submit, from the submitting thread;
@@ -260,18 +263,22 @@ typedef struct ace_server_s* ace_server;
 
 typedef enum { ACE_REQ_INSERT = 0, ACE_REQ_SCORE = 1 } ace_req_kind;
 
-/* Flag of ace_server_submit / ace_server_replay: the host rows (and, for scores, the host
- * outputs) are pinned memory (hipHostMalloc) that stays valid and unchanged until the
- * request completes; the copies then read and write them directly.  Without it the rows
- * are copied into the slot's staging before submit returns, and outputs are copied out by
- * the completion thread. */
+/* Flag of ace_server_submit / ace_server_replay: the host rows are pinned memory
+ * (hipHostMalloc).  If the request is at most gather_max_bytes and the runtime confirms
+ * that its rows lie inside one pinned allocation mapped at the same address on the device,
+ * a gather kernel of the batch reads them over the host link (one launch for all such
+ * requests of a batch); otherwise a host-to-device copy reads them.  Without the flag the rows are first copied into the slot's pinned
+ * staging.  Either way the rows must stay valid and unchanged until the request completes
+ * (and, with the flag, stay allocated). */
 #define ACE_SUBMIT_PINNED 1
 
 typedef struct {
-    int32_t slots;       /* 1..64 concurrent requests */
-    int32_t use_graphs;  /* must be 0 */
-    int64_t max_rows;    /* rows per request, 1..2^24 */
-    int64_t reserved;    /* must be 0 */
+    int32_t slots;              /* 1..64 batches in flight */
+    int32_t batch_rows;         /* a batch takes more requests only while it stays within this
+                                   many rows (0 = max_rows; a batch always takes one request) */
+    int64_t max_rows;           /* rows per request and per batch, 1..2^24 */
+    int64_t gather_max_bytes;   /* pinned requests of at most this many bytes of rows go to the
+                                   gather kernel, larger ones to a copy; 0 = 64 KiB, -1 = never */
 } ace_server_config;
 
 typedef struct {
@@ -289,17 +296,23 @@ typedef struct {
     double p50_ms, p99_ms, mean_ms, max_ms;   /* latency, arrival to completion */
     double p99_insert_ms, p99_score_ms;
     double wall_ms;                      /* first arrival to last completion */
+    int64_t batches;                     /* batches launched */
+    double mean_batch_requests;          /* requests per batch */
+    int64_t gathered_requests;           /* requests whose rows the gather kernel read */
+    double p50_queue_ms, p99_queue_ms;   /* arrival to the launch of the request's batch */
 } ace_server_stats;
 
 /* Create a server owning ctx's request stream.  ACE_E_INVALID on a bad config,
  * ACE_E_STATE if ctx already has a server, ACE_E_NOMEM if the slots do not fit. */
 ace_status ace_server_create(ace_ctx ctx, const ace_server_config* cfg, ace_server* out);
 
-/* Admit one request (blocks while every slot is busy).  X_host: FP32 [n][d] host rows.
- * Scores: s_host (FP32 [n]) and T_host (uint32 [n]) may each be NULL; they are filled when
- * the request completes.  *ticket (may be NULL) identifies it for ace_server_wait.
+/* Admit one request: queue it and return (blocks only while 65,536 requests are pending).
+ * X_host: FP32 [n][d] host rows, valid until the request completes.  Scores: s_host
+ * (FP32 [n]) and T_host (uint32 [n]) host buffers, each may be NULL, are filled when the
+ * request completes.  *ticket (may be NULL) identifies it for ace_server_wait.
  * ACE_E_INVALID for n outside 1..max_rows or a bad kind/flag; ACE_E_OVERFLOW as for
- * ace_insert / ace_score; a device error is sticky on the context and on the server. */
+ * ace_insert / ace_score (counting every admitted insert); a device error is sticky on the
+ * server: the failing batch, every later request and every later call report it. */
 ace_status ace_server_submit(ace_server srv, int32_t kind, const float* X_host, int64_t n, float* s_host,
                              uint32_t* T_host, int32_t flags, uint64_t* ticket);
 

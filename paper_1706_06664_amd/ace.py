@@ -78,15 +78,18 @@ class Counters(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("max_rows", ctypes.c_int64),
-                ("reserved", ctypes.c_int64)]
+    _fields_ = [("slots", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("max_rows", ctypes.c_int64),
+                ("gather_max_bytes", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("inserts", ctypes.c_int64), ("scores", ctypes.c_int64),
                 ("rows", ctypes.c_int64), ("insert_rows", ctypes.c_int64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("p99_insert_ms", ctypes.c_double), ("p99_score_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
+                ("p99_insert_ms", ctypes.c_double), ("p99_score_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("batches", ctypes.c_int64), ("mean_batch_requests", ctypes.c_double),
+                ("gathered_requests", ctypes.c_int64), ("p50_queue_ms", ctypes.c_double),
+                ("p99_queue_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -193,9 +196,10 @@ class ACE:
             _check(self.lib.ace_destroy(self.h), "ace_destroy")
             self.h = None
 
-    def server(self, slots: int = 4, max_rows: int = 65536) -> "Server":
-        """Attach a serving loop (request queue with `slots` concurrent requests)."""
-        return Server(self, slots, max_rows)
+    def server(self, slots: int = 4, max_rows: int = 65536, gather_max_bytes: int = 0,
+               batch_rows: int = 0) -> "Server":
+        """Attach a serving loop (request queue, `slots` batches in flight)."""
+        return Server(self, slots, max_rows, gather_max_bytes, batch_rows)
 
     def __del__(self):
         try:
@@ -323,11 +327,12 @@ class Server:
     """Serving loop of one ACE context: requests are admitted in order onto `slots`
     streams; a score sees exactly the inserts admitted before it."""
 
-    def __init__(self, ace: ACE, slots: int = 4, max_rows: int = 65536):
+    def __init__(self, ace: ACE, slots: int = 4, max_rows: int = 65536, gather_max_bytes: int = 0,
+                 batch_rows: int = 0):
         if getattr(ace, "_server", None) is not None:
             raise AceError(6, "ace_server_create")
         self.ace, self.lib, self.d = ace, ace.lib, ace.d
-        cfg = ServerConfig(int(slots), 0, int(max_rows), 0)
+        cfg = ServerConfig(int(slots), int(batch_rows), int(max_rows), int(gather_max_bytes))
         h = ctypes.c_void_p()
         _check(self.lib.ace_server_create(ace.h, ctypes.byref(cfg), ctypes.byref(h)), "ace_server_create")
         self.h = h
@@ -348,9 +353,9 @@ class Server:
             pass
 
     def submit(self, kind, X, s=None, T=None, pinned: bool = False) -> int:
-        """Admit one request.  X: host float32 [n][d].  For scores, s (float32 [n]) and T
-        (uint32 [n]) are host buffers filled when the request completes (keep them until
-        wait/drain).  pinned=True: X, s and T are pinned and stay untouched until then."""
+        """Queue one request.  X: host float32 [n][d].  For scores, s (float32 [n]) and T
+        (uint32 [n]) are host buffers filled when the request completes.  X, s and T are
+        held until wait/drain.  pinned=True: X is pinned memory, copied to the device directly."""
         k = _KINDS[kind] if isinstance(kind, str) else int(kind)
         n = int(X.shape[0])
         if X.shape[1] != self.d:

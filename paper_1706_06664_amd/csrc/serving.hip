@@ -1,18 +1,21 @@
 // Serving loop: a request queue in front of one ACE context.
 //
-// A request is a batch of rows to insert (counting phase of Alg. 1) or to score (query
-// phase).  Admission takes one of S slots; each slot owns a HIP stream, the hash
-// workspace, device buffers for its rows and outputs, and pinned host staging.  On its
-// slot's stream a request runs H2D copy -> hash -> count update (insert) or score + D2H
-// copy (score), then records the slot's event.  A completion thread polls the events of
-// busy slots, copies staged outputs to the caller, records the latency and frees the slot.
+// A request is a block of rows to insert (counting phase of Alg. 1) or to score (query
+// phase).  Submission appends it to a FIFO queue.  A dispatcher thread does continuous
+// batching: whenever one of S slots is free it takes the longest prefix of the queue that
+// fits batch_rows rows (at least one request), inserts and scores mixed, as one batch.  Each slot owns a
+// HIP stream, the hash workspace, device buffers for a batch and pinned host staging.  On
+// its stream a batch runs host-to-device copies -> one hash of all its rows -> the count
+// phase: one count-update or score launch per run of consecutive same-kind requests, in
+// admission order -> device-to-host copy of s and T.  A completion thread polls the
+// events of busy slots, copies each request's outputs to the caller, records its latency
+// and frees the slot.
 //
-// Ordering.  Inserts are integer adds and commute with each other; scores only read the
-// counts and commute with each other.  An insert and a score do not commute, so a request
-// waits (hipStreamWaitEvent, after its H2D copy) on the events of every request of the other
-// kind still in flight when it is admitted.  Requests that completed earlier are already
-// visible.  Hence a score sees exactly the inserts admitted before it, whatever S is: the
-// results equal those of running the requests one by one in admission order.
+// Ordering.  Hashing reads only the rows and W, so hashes of different batches overlap
+// freely.  The count phase of a batch waits (hipStreamWaitEvent) on the count phase of the
+// batch dispatched before it, so count phases run in admission order and a score sees
+// exactly the inserts admitted before it, whatever S is: the results equal those of
+// running the requests one at a time in admission order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +24,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -33,25 +37,74 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-struct Slot {
-    hipStream_t s = nullptr;
-    hipEvent_t done = nullptr;
-    Workspace ws;
-    float* Xd = nullptr;       // [max_rows][d] device rows
-    float* sd = nullptr;       // [max_rows] device scores
-    uint32_t* Td = nullptr;    // [max_rows] device totals
-    float* Xh = nullptr;       // pinned staging of the rows
-    float* sh = nullptr;       // pinned staging of the outputs
-    uint32_t* Th = nullptr;
-    // request in flight
-    bool busy = false;
+// Rows of one request, or part of it, that the gather kernel copies: src is a device-mapped
+// address of pinned host memory.
+struct GatherTask {
+    const float* src;
+    int32_t dst_row;
+    int32_t nrows;
+};
+constexpr int kGatherRows = 32;   // rows per task
+
+// One workgroup per task: copy nrows * d contiguous floats from pinned host memory (read
+// over the host link) into the batch's device rows.  16-byte loads when both ends allow.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const GatherTask* __restrict__ tasks, float* __restrict__ dst,
+                                                          int d) {
+    const GatherTask t = tasks[blockIdx.x];
+    const int64_t count = (int64_t)t.nrows * d;
+    float* o = dst + (int64_t)t.dst_row * d;
+    if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(t.src) & 15u) == 0)) {
+        const float4* s4 = reinterpret_cast<const float4*>(t.src);
+        float4* o4 = reinterpret_cast<float4*>(o);
+        const int64_t c4 = count >> 2;
+        int64_t i = threadIdx.x;
+        for (; i + 3 * 256 < c4; i += 4 * 256) {
+            const float4 a = s4[i], b = s4[i + 256], c = s4[i + 512], e = s4[i + 768];
+            o4[i] = a;
+            o4[i + 256] = b;
+            o4[i + 512] = c;
+            o4[i + 768] = e;
+        }
+        for (; i < c4; i += 256) o4[i] = s4[i];
+    } else {
+        for (int64_t i = threadIdx.x; i < count; i += 256) o[i] = t.src[i];
+    }
+}
+
+constexpr size_t kMaxPending = 1 << 16;   // admitted but not completed requests
+
+struct Req {
     int kind = 0;
     int64_t n = 0;
-    uint64_t ticket = 0;
+    const float* X = nullptr;
     float* s_user = nullptr;
     uint32_t* T_user = nullptr;
-    bool staged_out = false;
+    bool pinned = false;          // copy from X directly (no staging)
+    bool gather = false;          // X lies in device-mapped pinned memory: the gather kernel reads it
+    uint64_t ticket = 0;
+    int64_t off = 0;              // first row of the request inside its batch
     Clock::time_point t_arrive;
+};
+
+enum SlotState { SLOT_FREE = 0, SLOT_DISPATCHING = 1, SLOT_BUSY = 2 };
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;     // the whole batch (outputs copied back)
+    hipEvent_t cnt = nullptr;      // the batch's count phase (updates and scores)
+    Workspace ws;
+    float* Xd = nullptr;       // [max_rows][d] device rows of the batch
+    float* sd = nullptr;       // [max_rows] device scores
+    uint32_t* Td = nullptr;    // [max_rows] device totals
+    float* Xh = nullptr;       // pinned staging of pageable rows
+    float* sh = nullptr;       // pinned staging of the outputs
+    uint32_t* Th = nullptr;
+    GatherTask* tasks_h = nullptr;   // pinned: gather tasks of the batch
+    GatherTask* tasks_d = nullptr;   // device copy read by the gather kernel
+    int64_t task_cap = 0;
+    int state = SLOT_FREE;
+    bool has_score = false;
+    std::vector<Req> reqs;     // the batch in flight
 };
 
 double ms_between(Clock::time_point a, Clock::time_point b) {
@@ -64,97 +117,31 @@ struct ace_server_s {
     ace_ctx c = nullptr;
     ace_server_config cfg{};
     std::vector<Slot> slots;
-    std::mutex mu;                   // guards slot state, latency records, stats
-    std::condition_variable cv;      // a slot became free / busy, or a request completed
+    std::mutex mu;                   // guards everything below
+    std::condition_variable cv;      // queue, slot or completion state changed
     std::mutex submit_mu;            // one submitter at a time
-    std::thread completer;
+    std::thread dispatcher, completer;
     bool stop = false;
-    ace_status err = ACE_OK;         // first device error seen by the completion thread
+    ace_status err = ACE_OK;         // first device error (sticky)
     size_t bytes = 0;                // device bytes the slots hold (returned to the budget on destroy)
+    std::deque<Req> queue;           // admitted, not yet dispatched
+    int64_t pending = 0;             // admitted, not yet completed
+    int64_t busy = 0;                // slots in SLOT_BUSY
     uint64_t next_ticket = 0;
-    uint64_t ticket_base = 0;        // latency records start at this ticket
-    std::vector<double> latency_ms;  // per ticket since ticket_base (-1 while in flight)
-    std::vector<uint8_t> kind_of;    // per ticket since ticket_base
+    uint64_t ticket_base = 0;        // records start at this ticket
+    std::vector<double> latency_ms;  // per ticket since ticket_base (-1 until completed)
+    std::vector<double> queue_ms;    // per ticket: arrival to the launch of its batch
+    std::vector<uint8_t> done_of;
+    std::vector<uint8_t> kind_of;
     std::vector<int64_t> rows_of;
-    int64_t inflight = 0;
+    int64_t batches = 0, batched_requests = 0, gathered_requests = 0;
     int next_slot = 0;
+    int last_slot = -1;              // slot of the most recently dispatched batch
     bool have_first = false;
     Clock::time_point t_first, t_last;
 };
 
 namespace {
-
-void completion_loop(ace_server srv) {
-    (void)hipSetDevice(srv->c->cfg.device);
-    std::vector<int> busy;
-    for (;;) {
-        {
-            std::unique_lock<std::mutex> lk(srv->mu);
-            srv->cv.wait(lk, [&] { return srv->stop || srv->inflight > 0; });
-            if (srv->stop && srv->inflight == 0) return;
-            busy.clear();
-            for (int i = 0; i < (int)srv->slots.size(); ++i)
-                if (srv->slots[i].busy) busy.push_back(i);
-        }
-        bool any = false;
-        for (int i : busy) {
-            Slot& sl = srv->slots[i];
-            hipError_t q = hipEventQuery(sl.done);
-            if (q == hipErrorNotReady) continue;
-            ace_status st = ACE_OK;
-            if (q != hipSuccess) {
-                (void)hipGetLastError();
-                st = ACE_E_DEVICE;
-            } else if (sl.kind == ACE_REQ_SCORE && sl.staged_out) {
-                if (sl.s_user) std::memcpy(sl.s_user, sl.sh, sizeof(float) * (size_t)sl.n);
-                if (sl.T_user) std::memcpy(sl.T_user, sl.Th, sizeof(uint32_t) * (size_t)sl.n);
-            }
-            const Clock::time_point now = Clock::now();
-            {
-                std::lock_guard<std::mutex> lk(srv->mu);
-                if (st != ACE_OK && srv->err == ACE_OK) srv->err = st;
-                if (sl.ticket >= srv->ticket_base) srv->latency_ms[sl.ticket - srv->ticket_base] = ms_between(sl.t_arrive, now);
-                srv->t_last = now;
-                sl.busy = false;
-                --srv->inflight;
-            }
-            any = true;
-        }
-        if (any) srv->cv.notify_all();
-        else std::this_thread::yield();
-    }
-}
-
-void free_slot(ace_ctx c, Slot& sl) {
-    ws_free(&sl.ws);
-    void* dev[] = {sl.Xd, sl.sd, sl.Td};
-    for (void* p : dev)
-        if (p) (void)hipFree(p);
-    void* host[] = {sl.Xh, sl.sh, sl.Th};
-    for (void* p : host)
-        if (p) (void)hipHostFree(p);
-    if (sl.done) (void)hipEventDestroy(sl.done);
-    if (sl.s) (void)hipStreamDestroy(sl.s);
-    sl = Slot();
-}
-
-ace_status alloc_slot(ace_ctx c, Slot& sl, int64_t rows) {
-    const size_t d = (size_t)c->cfg.d;
-    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess) return ACE_E_DEVICE;
-    if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) return ACE_E_DEVICE;
-    ace_status st = ws_alloc(c, &sl.ws, rows);
-    st = st ? st : dev_alloc(c, (void**)&sl.Xd, sizeof(float) * d * (size_t)rows);
-    st = st ? st : dev_alloc(c, (void**)&sl.sd, sizeof(float) * (size_t)rows);
-    st = st ? st : dev_alloc(c, (void**)&sl.Td, sizeof(uint32_t) * (size_t)rows);
-    if (st) return st;
-    if (hipHostMalloc((void**)&sl.Xh, sizeof(float) * d * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&sl.sh, sizeof(float) * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&sl.Th, sizeof(uint32_t) * (size_t)rows, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return ACE_E_NOMEM;
-    }
-    return ACE_OK;
-}
 
 struct DevGuard {
     int prev = -1;
@@ -167,104 +154,313 @@ struct DevGuard {
     }
 };
 
-// Enqueue one admitted request on its slot's stream.  Called with submit_mu held.
-ace_status enqueue(ace_server srv, Slot& sl, int kind, const float* X, int64_t n, int32_t flags,
-                   const std::vector<hipEvent_t>& waits) {
-    ace_ctx c = srv->c;
-    const size_t xbytes = sizeof(float) * (size_t)c->cfg.d * (size_t)n;
-    const float* src = X;
-    if (!(flags & ACE_SUBMIT_PINNED)) {
-        std::memcpy(sl.Xh, X, xbytes);
-        src = sl.Xh;
+// Mark the requests of a batch complete (called with mu held).
+void complete_locked(ace_server srv, std::vector<Req>& reqs, Clock::time_point now, bool ok) {
+    for (const Req& q : reqs) {
+        if (q.ticket >= srv->ticket_base) {
+            const size_t i = q.ticket - srv->ticket_base;
+            srv->latency_ms[i] = ok ? ms_between(q.t_arrive, now) : -1.0;
+            srv->done_of[i] = 1;
+        }
+        --srv->pending;
     }
-    ace_status st = check(c, hipMemcpyAsync(sl.Xd, src, xbytes, hipMemcpyHostToDevice, sl.s));
-    for (hipEvent_t e : waits)
-        st = st ? st : check(c, hipStreamWaitEvent(sl.s, e, 0));
-    st = st ? st : hash_chunk(c, &sl.ws, sl.Xd, n, false, sl.s);
-    if (st) return st;
-    if (kind == ACE_REQ_INSERT) {
-        st = check(c, launch_count_update(sl.ws.codes, n, n, c->cfg.K, c->cfg.L, +1, c->counts, c->S2, c->S3, c->err,
-                                          sl.s));
-    } else {
-        st = check(c, launch_score(sl.ws.codes, n, n, c->cfg.K, c->cfg.L, c->counts, sl.sd, sl.Td, c->mom, sl.s));
-        if (st) return st;
-        float* so = sl.staged_out ? sl.sh : sl.s_user;
-        uint32_t* To = sl.staged_out ? sl.Th : sl.T_user;
-        if (so && sl.s_user) st = check(c, hipMemcpyAsync(so, sl.sd, sizeof(float) * n, hipMemcpyDeviceToHost, sl.s));
-        if (!st && To && sl.T_user)
-            st = check(c, hipMemcpyAsync(To, sl.Td, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, sl.s));
-    }
-    if (st) return st;
-    return check(c, hipEventRecord(sl.done, sl.s));
+    srv->t_last = now;
+    reqs.clear();
 }
 
+void completion_loop(ace_server srv) {
+    (void)hipSetDevice(srv->c->cfg.device);
+    std::vector<int> busy;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv.wait(lk, [&] { return srv->stop || srv->busy > 0; });
+            if (srv->stop && srv->busy == 0) return;
+            busy.clear();
+            for (int i = 0; i < (int)srv->slots.size(); ++i)
+                if (srv->slots[i].state == SLOT_BUSY) busy.push_back(i);
+        }
+        bool any = false;
+        for (int i : busy) {
+            Slot& sl = srv->slots[i];
+            hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            const bool ok = q == hipSuccess;
+            if (!ok) (void)hipGetLastError();
+            if (ok && sl.has_score) {
+                for (const Req& r : sl.reqs) {
+                    if (r.kind != ACE_REQ_SCORE) continue;
+                    if (r.s_user) std::memcpy(r.s_user, sl.sh + r.off, sizeof(float) * (size_t)r.n);
+                    if (r.T_user) std::memcpy(r.T_user, sl.Th + r.off, sizeof(uint32_t) * (size_t)r.n);
+                }
+            }
+            const Clock::time_point now = Clock::now();
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                if (!ok && srv->err == ACE_OK) srv->err = ACE_E_DEVICE;
+                complete_locked(srv, sl.reqs, now, ok);
+                sl.state = SLOT_FREE;
+                --srv->busy;
+            }
+            any = true;
+        }
+        if (any) srv->cv.notify_all();
+        else std::this_thread::yield();
+    }
+}
+
+// Enqueue one batch on its slot's stream (dispatcher thread, no lock held).
+ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait_cnt) {
+    ace_ctx c = srv->c;
+    const size_t d = (size_t)c->cfg.d;
+    ace_status st = ACE_OK;
+    // Host-to-device copies of the rows; adjacent sources are merged into one copy.
+    const float* run_src = nullptr;
+    int64_t run_off = 0, run_n = 0;
+    auto flush = [&] {
+        if (run_n > 0 && !st)
+            st = check(c, hipMemcpyAsync(sl.Xd + (size_t)run_off * d, run_src, sizeof(float) * d * (size_t)run_n,
+                                         hipMemcpyHostToDevice, sl.s));
+        run_n = 0;
+    };
+    int64_t ntask = 0;
+    for (const Req& q : sl.reqs) {
+        if (q.gather) {
+            for (int64_t r = 0; r < q.n; r += kGatherRows)
+                sl.tasks_h[ntask++] = GatherTask{q.X + (size_t)r * d, (int32_t)(q.off + r),
+                                                 (int32_t)(q.n - r < kGatherRows ? q.n - r : kGatherRows)};
+            continue;
+        }
+        const float* src = q.X;
+        if (!q.pinned) {
+            std::memcpy(sl.Xh + (size_t)q.off * d, q.X, sizeof(float) * d * (size_t)q.n);
+            src = sl.Xh + (size_t)q.off * d;
+        }
+        if (run_n > 0 && src == run_src + (size_t)run_n * d) {
+            run_n += q.n;
+        } else {
+            flush();
+            run_src = src;
+            run_off = q.off;
+            run_n = q.n;
+        }
+    }
+    flush();
+    if (ntask > 0) {
+        st = st ? st : check(c, hipMemcpyAsync(sl.tasks_d, sl.tasks_h, sizeof(GatherTask) * (size_t)ntask,
+                                               hipMemcpyHostToDevice, sl.s));
+        if (!st) {
+            hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)ntask), dim3(256), 0, sl.s, sl.tasks_d, sl.Xd,
+                               (int)d);
+            st = check(c, hipGetLastError());
+        }
+    }
+    // Hashing does not read the counts: it overlaps with the batches in flight.
+    st = st ? st : hash_chunk(c, &sl.ws, sl.Xd, rows, false, sl.s);
+    // Count phase, after the previous batch's count phase: one launch per run of
+    // consecutive requests of one kind, in admission order.
+    if (wait_cnt) st = st ? st : check(c, hipStreamWaitEvent(sl.s, wait_cnt, 0));
+    size_t i = 0;
+    while (!st && i < sl.reqs.size()) {
+        const int kind = sl.reqs[i].kind;
+        const int64_t off = sl.reqs[i].off;
+        int64_t len = 0;
+        for (; i < sl.reqs.size() && sl.reqs[i].kind == kind; ++i) len += sl.reqs[i].n;
+        const uint16_t* codes = sl.ws.codes + off;   // table j of row r at codes[j * rows + r]
+        if (kind == ACE_REQ_INSERT)
+            st = check(c, launch_count_update(codes, rows, len, c->cfg.K, c->cfg.L, +1, c->counts, c->S2, c->S3,
+                                              c->err, sl.s));
+        else
+            st = check(c, launch_score(codes, rows, len, c->cfg.K, c->cfg.L, c->counts, sl.sd + off, sl.Td + off,
+                                       c->mom, sl.s));
+    }
+    st = st ? st : check(c, hipEventRecord(sl.cnt, sl.s));
+    if (sl.has_score) {
+        st = st ? st : check(c, hipMemcpyAsync(sl.sh, sl.sd, sizeof(float) * rows, hipMemcpyDeviceToHost, sl.s));
+        st = st ? st : check(c, hipMemcpyAsync(sl.Th, sl.Td, sizeof(uint32_t) * rows, hipMemcpyDeviceToHost, sl.s));
+    }
+    return st ? st : check(c, hipEventRecord(sl.done, sl.s));
+}
+
+// Continuous batching: whenever a slot is free, the longest prefix of the queue that fits
+// batch_rows rows (at least one request, each <= max_rows) becomes one batch.
+void dispatch_loop(ace_server srv) {
+    (void)hipSetDevice(srv->c->cfg.device);
+    const int S = (int)srv->slots.size();
+    for (;;) {
+        hipEvent_t wait_cnt = nullptr;
+        int idx = -1;
+        int64_t rows = 0;
+        ace_status prior = ACE_OK;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv.wait(lk, [&] {
+                if (srv->stop && srv->queue.empty()) return true;
+                if (srv->queue.empty()) return false;
+                for (int k = 0; k < S; ++k)
+                    if (srv->slots[(srv->next_slot + k) % S].state == SLOT_FREE) return true;
+                return false;
+            });
+            if (srv->queue.empty()) return;   // stop requested and nothing left
+            for (int k = 0; k < S && idx < 0; ++k)
+                if (srv->slots[(srv->next_slot + k) % S].state == SLOT_FREE) idx = (srv->next_slot + k) % S;
+            srv->next_slot = (idx + 1) % S;
+            Slot& sl = srv->slots[idx];
+            sl.state = SLOT_DISPATCHING;
+            sl.reqs.clear();
+            sl.has_score = false;
+            while (!srv->queue.empty() && (rows == 0 || rows + srv->queue.front().n <= srv->cfg.batch_rows)) {
+                Req q = srv->queue.front();
+                srv->queue.pop_front();
+                q.off = rows;
+                rows += q.n;
+                sl.has_score |= q.kind == ACE_REQ_SCORE;
+                sl.reqs.push_back(q);
+            }
+            // The previous batch's slot cannot be dispatched again before this batch, so its
+            // count event still marks that batch (complete already if the slot is free).
+            if (srv->last_slot >= 0 && srv->last_slot != idx) wait_cnt = srv->slots[srv->last_slot].cnt;
+            srv->last_slot = idx;
+            prior = srv->err;
+        }
+        Slot& sl = srv->slots[idx];
+        // After a device error every later batch completes unlaunched, with the error.
+        ace_status st = prior != ACE_OK ? prior : enqueue_batch(srv, sl, rows, wait_cnt);
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (st != ACE_OK) {
+                if (srv->err == ACE_OK) srv->err = st;
+                complete_locked(srv, sl.reqs, Clock::now(), false);
+                sl.state = SLOT_FREE;
+            } else {
+                const Clock::time_point now = Clock::now();
+                for (const Req& q : sl.reqs)
+                    if (q.ticket >= srv->ticket_base) srv->queue_ms[q.ticket - srv->ticket_base] = ms_between(q.t_arrive, now);
+                sl.state = SLOT_BUSY;
+                ++srv->busy;
+                ++srv->batches;
+                srv->batched_requests += (int64_t)sl.reqs.size();
+                for (const Req& q : sl.reqs) srv->gathered_requests += q.gather ? 1 : 0;
+            }
+        }
+        srv->cv.notify_all();
+    }
+}
+
+void free_slot(Slot& sl) {
+    ws_free(&sl.ws);
+    void* dev[] = {sl.Xd, sl.sd, sl.Td, sl.tasks_d};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    void* host[] = {sl.Xh, sl.sh, sl.Th, sl.tasks_h};
+    for (void* p : host)
+        if (p) (void)hipHostFree(p);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.cnt) (void)hipEventDestroy(sl.cnt);
+    if (sl.s) (void)hipStreamDestroy(sl.s);
+    sl = Slot();
+}
+
+ace_status alloc_slot(ace_ctx c, Slot& sl, int64_t rows) {
+    const size_t d = (size_t)c->cfg.d;
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess) return ACE_E_DEVICE;
+    if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) return ACE_E_DEVICE;
+    if (hipEventCreateWithFlags(&sl.cnt, hipEventDisableTiming) != hipSuccess) return ACE_E_DEVICE;
+    ace_status st = ws_alloc(c, &sl.ws, rows);
+    st = st ? st : dev_alloc(c, (void**)&sl.Xd, sizeof(float) * d * (size_t)rows);
+    st = st ? st : dev_alloc(c, (void**)&sl.sd, sizeof(float) * (size_t)rows);
+    st = st ? st : dev_alloc(c, (void**)&sl.Td, sizeof(uint32_t) * (size_t)rows);
+    // A batch of `rows` rows made of requests of >= 1 row needs at most
+    // rows / kGatherRows + (number of requests) <= rows / kGatherRows + rows tasks.
+    sl.task_cap = rows / kGatherRows + rows + 1;
+    st = st ? st : dev_alloc(c, (void**)&sl.tasks_d, sizeof(GatherTask) * (size_t)sl.task_cap);
+    if (st) return st;
+    if (hipHostMalloc((void**)&sl.Xh, sizeof(float) * d * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sl.sh, sizeof(float) * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sl.Th, sizeof(uint32_t) * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sl.tasks_h, sizeof(GatherTask) * (size_t)sl.task_cap, hipHostMallocDefault) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return ACE_E_NOMEM;
+    }
+    return ACE_OK;
+}
+
+// True iff [X, X + bytes) lies inside one pinned host allocation that the device reads at
+// the same address, as the runtime reports it.  Only such rows go to the gather kernel;
+// anything else is copied by the runtime's DMA, which checks its own source.
+bool device_mapped_pinned(const float* X, size_t bytes) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, X) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeHost || a.devicePointer != (const void*)X) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)X) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), x = reinterpret_cast<uintptr_t>(X);
+    return x >= b && bytes <= size && x - b <= size - bytes;
+}
+
+// gather: -1 = decide here (size, pinned flag and runtime check); 0 = never; 1 = the caller
+// checked the rows (only the size is checked here).
 ace_status submit_at(ace_server srv, int32_t kind, const float* X, int64_t n, float* s_host, uint32_t* T_host,
-                     int32_t flags, Clock::time_point t_arrive, uint64_t* ticket) {
+                     int32_t flags, Clock::time_point t_arrive, uint64_t* ticket, int gather = -1) {
     ace_ctx c = srv->c;
     if (kind != ACE_REQ_INSERT && kind != ACE_REQ_SCORE) return ACE_E_INVALID;
     if (n < 1 || n > srv->cfg.max_rows || !X) return ACE_E_INVALID;
     if (flags & ~ACE_SUBMIT_PINNED) return ACE_E_INVALID;
-    if (c->sticky != ACE_OK) return c->sticky;
     std::lock_guard<std::mutex> sub(srv->submit_mu);
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->err != ACE_OK) return srv->err;
-    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->err != ACE_OK) return srv->err;
+    // n_total counts every admitted insert, so the guards hold for any interleaving.
     if (kind == ACE_REQ_INSERT && c->n_total + n > c->cap) return ACE_E_OVERFLOW;
     if (kind == ACE_REQ_SCORE && (u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull) return ACE_E_OVERFLOW;
     if (c->fail_next) {
         c->fail_next = 0;
-        c->sticky = ACE_E_DEVICE;
+        srv->err = ACE_E_DEVICE;
         return ACE_E_DEVICE;
     }
-    // Admission: wait for a free slot; collect the events of in-flight requests of the
-    // other kind.
-    int idx = -1;
-    std::vector<hipEvent_t> waits;
-    {
-        std::unique_lock<std::mutex> lk(srv->mu);
-        const int S = (int)srv->slots.size();
-        srv->cv.wait(lk, [&] {
-            for (int k = 0; k < S; ++k)
-                if (!srv->slots[(srv->next_slot + k) % S].busy) return true;
-            return false;
-        });
-        for (int k = 0; k < S; ++k) {
-            const int i = (srv->next_slot + k) % S;
-            if (!srv->slots[i].busy) {
-                idx = i;
-                break;
-            }
+    srv->cv.wait(lk, [&] { return srv->pending < (int64_t)kMaxPending || srv->err != ACE_OK; });
+    if (srv->err != ACE_OK) return srv->err;
+    const size_t bytes = sizeof(float) * (size_t)c->cfg.d * (size_t)n;
+    if ((int64_t)bytes > srv->cfg.gather_max_bytes) {
+        gather = 0;   // a copy moves large requests faster than the gather kernel
+    } else if (gather < 0) {
+        gather = 0;
+        if (flags & ACE_SUBMIT_PINNED) {
+            DevGuard g(c->cfg.device);
+            gather = device_mapped_pinned(X, bytes) ? 1 : 0;
         }
-        srv->next_slot = (idx + 1) % S;
-        for (auto& o : srv->slots)
-            if (o.busy && o.kind != kind) waits.push_back(o.done);
     }
-    Slot& sl = srv->slots[idx];
-    sl.kind = kind;
-    sl.n = n;
-    sl.s_user = s_host;
-    sl.T_user = T_host;
-    sl.staged_out = !(flags & ACE_SUBMIT_PINNED);
-    sl.t_arrive = t_arrive;
-    DevGuard g(c->cfg.device);
-    ace_status st = enqueue(srv, sl, kind, X, n, flags, waits);
-    if (st) return st;
+    Req q;
+    q.gather = gather == 1;
+    q.kind = kind;
+    q.n = n;
+    q.X = X;
+    q.s_user = s_host;
+    q.T_user = T_host;
+    q.pinned = (flags & ACE_SUBMIT_PINNED) != 0;
+    q.t_arrive = t_arrive;
+    q.ticket = srv->next_ticket++;
     if (kind == ACE_REQ_INSERT) c->n_total += n;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        sl.ticket = srv->next_ticket++;
-        srv->latency_ms.push_back(-1.0);
-        srv->kind_of.push_back((uint8_t)kind);
-        srv->rows_of.push_back(n);
-        if (!srv->have_first) {
-            srv->have_first = true;
-            srv->t_first = t_arrive;
-        }
-        sl.busy = true;
-        ++srv->inflight;
-        if (ticket) *ticket = sl.ticket;
+    srv->latency_ms.push_back(-1.0);
+    srv->queue_ms.push_back(-1.0);
+    srv->done_of.push_back(0);
+    srv->kind_of.push_back((uint8_t)kind);
+    srv->rows_of.push_back(n);
+    if (!srv->have_first) {
+        srv->have_first = true;
+        srv->t_first = t_arrive;
     }
+    ++srv->pending;
+    srv->queue.push_back(q);
+    if (ticket) *ticket = q.ticket;
+    lk.unlock();
     srv->cv.notify_all();
     return ACE_OK;
 }
@@ -278,6 +474,11 @@ double percentile(std::vector<double>& v, double p) {
     return v[r - 1];
 }
 
+ace_status drain_locked(ace_server srv, std::unique_lock<std::mutex>& lk) {
+    srv->cv.wait(lk, [&] { return srv->pending == 0; });
+    return srv->err;
+}
+
 }  // namespace
 
 extern "C" {
@@ -286,12 +487,14 @@ ace_status ace_server_create(ace_ctx c, const ace_server_config* cfg, ace_server
     if (!c || !cfg || !out) return ACE_E_INVALID;
     if (c->sticky != ACE_OK) return c->sticky;
     if (cfg->slots < 1 || cfg->slots > 64 || cfg->max_rows < 1 || cfg->max_rows > ((int64_t)1 << 24)) return ACE_E_INVALID;
-    if (cfg->use_graphs != 0 || cfg->reserved != 0) return ACE_E_INVALID;
+    if (cfg->batch_rows < 0 || cfg->gather_max_bytes < -1) return ACE_E_INVALID;
     if (c->server_attached) return ACE_E_STATE;
     DevGuard g(c->cfg.device);
     ace_server srv = new ace_server_s();
     srv->c = c;
     srv->cfg = *cfg;
+    if (srv->cfg.gather_max_bytes == 0) srv->cfg.gather_max_bytes = 64 * 1024;
+    if (srv->cfg.batch_rows == 0 || srv->cfg.batch_rows > srv->cfg.max_rows) srv->cfg.batch_rows = (int32_t)srv->cfg.max_rows;
     srv->slots.resize(cfg->slots);
     const size_t bytes0 = c->bytes;
     ace_status st = ACE_OK;
@@ -301,13 +504,14 @@ ace_status ace_server_create(ace_ctx c, const ace_server_config* cfg, ace_server
     }
     srv->bytes = c->bytes - bytes0;
     if (st) {
-        for (auto& sl : srv->slots) free_slot(c, sl);
+        for (auto& sl : srv->slots) free_slot(sl);
         c->bytes -= srv->bytes;
         delete srv;
         return st;
     }
     c->server_attached = 1;
     srv->completer = std::thread(completion_loop, srv);
+    srv->dispatcher = std::thread(dispatch_loop, srv);
     *out = srv;
     return ACE_OK;
 }
@@ -322,13 +526,7 @@ ace_status ace_server_wait(ace_server srv, uint64_t ticket, double* latency_ms) 
     if (!srv) return ACE_E_INVALID;
     std::unique_lock<std::mutex> lk(srv->mu);
     if (ticket >= srv->next_ticket) return ACE_E_INVALID;
-    auto done = [&] {
-        if (srv->err != ACE_OK) return true;
-        for (auto& sl : srv->slots)
-            if (sl.busy && sl.ticket == ticket) return false;
-        return true;
-    };
-    srv->cv.wait(lk, done);
+    srv->cv.wait(lk, [&] { return ticket < srv->ticket_base || srv->done_of[ticket - srv->ticket_base]; });
     if (latency_ms)
         *latency_ms = ticket >= srv->ticket_base ? srv->latency_ms[ticket - srv->ticket_base] : -1.0;
     return srv->err;
@@ -338,23 +536,30 @@ ace_status ace_server_drain(ace_server srv) {
     if (!srv) return ACE_E_INVALID;
     std::lock_guard<std::mutex> sub(srv->submit_mu);
     std::unique_lock<std::mutex> lk(srv->mu);
-    srv->cv.wait(lk, [&] { return srv->inflight == 0; });
-    return srv->err != ACE_OK ? srv->err : srv->c->sticky;
+    return drain_locked(srv, lk);
 }
 
 ace_status ace_server_replay(ace_server srv, const ace_request* reqs, int64_t nreq, const float* pool,
                              int64_t pool_rows, int32_t flags, float* s_out, uint32_t* T_out, double* latency_ms) {
-    if (!srv || (nreq > 0 && (!reqs || !pool))) return ACE_E_INVALID;
-    if (nreq < 0 || pool_rows < 0 || (flags & ~ACE_SUBMIT_PINNED)) return ACE_E_INVALID;
+    if (!srv || nreq < 0 || (nreq > 0 && (!reqs || !pool))) return ACE_E_INVALID;
+    if (pool_rows < 0 || (flags & ~ACE_SUBMIT_PINNED)) return ACE_E_INVALID;
     for (int64_t r = 0; r < nreq; ++r) {
         const ace_request& q = reqs[r];
-        if (q.n < 1 || q.row0 < 0 || q.row0 + q.n > pool_rows || q.t_arrival_s < 0) return ACE_E_INVALID;
+        if (q.kind != ACE_REQ_INSERT && q.kind != ACE_REQ_SCORE) return ACE_E_INVALID;
+        if (q.n < 1 || q.n > srv->cfg.max_rows || q.row0 < 0 || q.row0 > pool_rows - q.n) return ACE_E_INVALID;
+        if (!(q.t_arrival_s >= 0)) return ACE_E_INVALID;
         if (q.kind == ACE_REQ_SCORE && (s_out || T_out) && q.out0 < 0) return ACE_E_INVALID;
     }
     const size_t d = (size_t)srv->c->cfg.d;
+    int gather = 0;
+    if ((flags & ACE_SUBMIT_PINNED) && nreq > 0) {
+        DevGuard g(srv->c->cfg.device);
+        gather = device_mapped_pinned(pool, sizeof(float) * d * (size_t)pool_rows) ? 1 : 0;
+    }
     std::vector<uint64_t> tickets((size_t)nreq);
     const Clock::time_point t0 = Clock::now();
-    for (int64_t r = 0; r < nreq; ++r) {
+    ace_status st = ACE_OK;
+    for (int64_t r = 0; r < nreq && !st; ++r) {
         const ace_request& q = reqs[r];
         Clock::time_point ta = Clock::now();
         if (q.t_arrival_s > 0) {
@@ -363,30 +568,29 @@ ace_status ace_server_replay(ace_server srv, const ace_request* reqs, int64_t nr
         }
         float* so = (q.kind == ACE_REQ_SCORE && s_out) ? s_out + q.out0 : nullptr;
         uint32_t* To = (q.kind == ACE_REQ_SCORE && T_out) ? T_out + q.out0 : nullptr;
-        ace_status st = submit_at(srv, q.kind, pool + (size_t)q.row0 * d, q.n, so, To, flags, ta, &tickets[r]);
-        if (st) {
-            (void)ace_server_drain(srv);
-            return st;
-        }
+        st = submit_at(srv, q.kind, pool + (size_t)q.row0 * d, q.n, so, To, flags, ta, &tickets[r], gather);
     }
-    ace_status st = ace_server_drain(srv);
+    const ace_status st2 = ace_server_drain(srv);
     if (latency_ms) {
         std::lock_guard<std::mutex> lk(srv->mu);
         for (int64_t r = 0; r < nreq; ++r)
-            latency_ms[r] = tickets[r] >= srv->ticket_base ? srv->latency_ms[tickets[r] - srv->ticket_base] : -1.0;
+            latency_ms[r] = tickets[r] >= srv->ticket_base && tickets[r] < srv->next_ticket
+                                ? srv->latency_ms[tickets[r] - srv->ticket_base]
+                                : -1.0;
     }
-    return st;
+    return st ? st : st2;
 }
 
 ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     if (!srv || !out) return ACE_E_INVALID;
     std::lock_guard<std::mutex> lk(srv->mu);
     ace_server_stats s{};
-    std::vector<double> all, ins, sco;
+    std::vector<double> all, ins, sco, qw;
     for (size_t i = 0; i < srv->latency_ms.size(); ++i) {
+        if (!srv->done_of[i] || srv->latency_ms[i] < 0) continue;
         const double v = srv->latency_ms[i];
-        if (v < 0) continue;
         all.push_back(v);
+        qw.push_back(srv->queue_ms[i]);
         (srv->kind_of[i] == ACE_REQ_INSERT ? ins : sco).push_back(v);
         s.rows += srv->rows_of[i];
         if (srv->kind_of[i] == ACE_REQ_INSERT) s.insert_rows += srv->rows_of[i];
@@ -406,6 +610,11 @@ ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     s.p99_insert_ms = percentile(ins, 99.0);
     s.p99_score_ms = percentile(sco, 99.0);
     s.wall_ms = srv->have_first ? ms_between(srv->t_first, srv->t_last) : 0.0;
+    s.batches = srv->batches;
+    s.mean_batch_requests = srv->batches ? (double)srv->batched_requests / (double)srv->batches : 0.0;
+    s.gathered_requests = srv->gathered_requests;
+    s.p50_queue_ms = percentile(qw, 50.0);
+    s.p99_queue_ms = percentile(qw, 99.0);
     *out = s;
     return ACE_OK;
 }
@@ -414,11 +623,14 @@ ace_status ace_server_reset_stats(ace_server srv) {
     if (!srv) return ACE_E_INVALID;
     std::lock_guard<std::mutex> sub(srv->submit_mu);
     std::unique_lock<std::mutex> lk(srv->mu);
-    srv->cv.wait(lk, [&] { return srv->inflight == 0; });
+    (void)drain_locked(srv, lk);
     srv->ticket_base = srv->next_ticket;
     srv->latency_ms.clear();
+    srv->queue_ms.clear();
+    srv->done_of.clear();
     srv->kind_of.clear();
     srv->rows_of.clear();
+    srv->batches = srv->batched_requests = srv->gathered_requests = 0;
     srv->have_first = false;
     return ACE_OK;
 }
@@ -431,11 +643,12 @@ ace_status ace_server_destroy(ace_server srv) {
         srv->stop = true;
     }
     srv->cv.notify_all();
+    srv->dispatcher.join();
     srv->completer.join();
     DevGuard g(srv->c->cfg.device);
     for (auto& sl : srv->slots) {
         (void)hipStreamSynchronize(sl.s);
-        free_slot(srv->c, sl);
+        free_slot(sl);
     }
     srv->c->bytes -= srv->bytes;
     srv->c->server_attached = 0;

@@ -101,4 +101,4 @@ def test_request_record_layout_matches_header():
     assert [REQUEST_DTYPE.fields[f][1] for f in ("kind", "pad", "n", "row0", "out0", "t_arrival_s")] == \
         [0, 4, 8, 16, 24, 32]
     assert ctypes.sizeof(ServerConfig) == 24
-    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8
+    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16

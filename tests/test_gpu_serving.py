@@ -46,9 +46,16 @@ def _oracle_replay(kind, n, row0, out0, pool, W, K, L):
     return T, sk, int(np.count_nonzero(amb))
 
 
-@pytest.mark.parametrize("precision,d,slots,nreq", [("fp32", 64, 1, 300), ("fp32", 64, 8, 300),
-                                                    ("bf16", 256, 4, 200), ("fp8", 256, 6, 200)])
-def test_serving_equals_sequential_replay(precision, d, slots, nreq):
+@pytest.mark.parametrize("precision,d,slots,nreq,pinned,gmb,br", [
+    ("fp32", 64, 1, 300, False, 0, 0), ("fp32", 64, 8, 300, False, 0, 0), ("fp32", 61, 3, 300, True, 1 << 30, 0),
+    ("fp32", 64, 4, 300, True, 0, 100), ("bf16", 256, 4, 200, True, 0, 0), ("bf16", 256, 2, 200, False, 0, 0),
+    ("fp8", 256, 6, 200, True, -1, 0)])
+def test_serving_equals_sequential_replay(precision, d, slots, nreq, pinned, gmb, br):
+    """Closed loop (every request queued at once), so batches mix inserts and scores.  With
+    pinned rows, requests of at most gmb bytes are read by the gather kernel (d=61 takes its
+    unaligned path), larger ones by copies (0: the 64 KiB default, -1: never gather).
+    br: target rows per batch (0 = max_rows)."""
+    import torch
     from paper_1706_06664_amd import ACE
     K, L = 15, 50
     kind, n, row0, out0, t, pool = serving_trace(nreq, d, seed=5, median_batch=32, max_batch=1024)
@@ -57,13 +64,20 @@ def test_serving_equals_sequential_replay(precision, d, slots, nreq):
     assert n_amb == 0   # continuous rows: no projection inside the FP64 margin
     _say(dict(precision=precision, slots=slots, requests=nreq, rows=int(n.sum()), scored=int(T_o.size)))
     ace = ACE(W, K, L, precision=precision, refine=True)
-    srv = ace.server(slots=slots, max_rows=1024)
+    srv = ace.server(slots=slots, max_rows=1024, gather_max_bytes=gmb, batch_rows=br)
     s_out = np.full(T_o.size, -1.0, np.float32)
     T_out = np.zeros(T_o.size, np.uint32)
-    lat = srv.replay(_records(kind, n, row0, out0, np.zeros_like(t)), pool, s_out, T_out)
+    src = torch.from_numpy(pool).pin_memory() if pinned else pool
+    lat = srv.replay(_records(kind, n, row0, out0, np.zeros_like(t)), src, s_out, T_out, pinned=pinned)
     st = srv.stats()
     _say(st)
     assert st["requests"] == nreq and st["rows"] == int(n.sum())
+    lim = {0: 64 * 1024, -1: -1}.get(gmb, gmb)
+    assert st["gathered_requests"] == (int((4 * d * n <= lim).sum()) if pinned else 0)
+    if pinned and gmb == 0 and d == 256:   # requests above 64 KiB take copies
+        assert 0 < st["gathered_requests"] < nreq
+    if br:
+        assert st["batches"] >= int(n.sum()) // 1024 and st["mean_batch_requests"] < nreq / 20
     assert (lat >= 0).all()
     np.testing.assert_array_equal(T_out.astype(np.int64), T_o)
     np.testing.assert_allclose(s_out, T_o / L, rtol=1e-6, atol=0)
@@ -92,7 +106,7 @@ def test_submit_wait_pageable_and_pinned():
         if kind[r] == 0:
             srv.submit("insert", np.ascontiguousarray(X))
             continue
-        if r % 2:   # pinned buffers, read and written directly by the copies
+        if r % 2:   # pinned rows: read by the gather kernel
             Xp = torch.from_numpy(np.ascontiguousarray(X)).pin_memory()
             T = torch.zeros(int(n[r]), dtype=torch.int32).pin_memory()
             s = torch.zeros(int(n[r]), dtype=torch.float32).pin_memory()
@@ -113,6 +127,7 @@ def test_submit_wait_pageable_and_pinned():
     srv.drain()
     st = srv.stats()
     assert st["requests"] == len(kind)
+    assert st["gathered_requests"] == sum(1 for r, *_ in outs if r % 2)
     srv.close()
     ace.close()
 
