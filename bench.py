@@ -262,6 +262,54 @@ def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536)
     return out
 
 
+def exact_score_runs(X, W, K, n_queries=4096, reps=5):
+    """Exact S(q, D) (Eq. thescore) of n_queries rows of the connection-log workload against
+    all of its rows, timed with HIP events on the launch stream (FP64 matrix roofline:
+    2 m n d FLOP per launch), then the estimator study of Sec. 3 on the same queries: the
+    ACE estimate T/L at several L against the exact S (relative RMSE), beside the standard
+    deviation of uniform sampling with L points, sqrt((n sum p^2K - S^2) / L) (Theorem 2's
+    comparison)."""
+    import numpy as np
+    import torch
+    from ace_inputs import projection_matrix
+    from paper_1706_06664_amd import ACE, exact_score
+    n, d = X.shape
+    Xd = torch.from_numpy(X).to("cuda:0")
+    idx = torch.from_numpy(np.linspace(0, n - 1, n_queries).astype(np.int64)).to("cuda:0")
+    Qd = Xd[idx].contiguous()
+    S, S2 = exact_score(Qd, Xd, K, want_S2=True)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        exact_score(Qd, Xd, K, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flop = 2.0 * n_queries * n * d
+    out = {"workload": f"exact S of {n_queries} connection-log rows against {n}x{d}, K={K}",
+           "ms_per_launch": ms, "pairs_per_s": n_queries * n / (ms / 1e3),
+           "roofline": {"bound": "mfma", "achieved": flop / (ms / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": flop / (ms / 1e3) / 78.6e12, "kernel": "exact_score_kernel (FP64 MFMA + arccos)"}}
+    S, S2 = S.double(), S2.double()
+    study = []
+    for L in (10, 20, 50, 100, 200):
+        Wl = projection_matrix(d, K, L, 1706066700 + L)
+        a = ACE(Wl, K, L)
+        a.insert(Xd)
+        s, _ = a.score(Qd)
+        a.close()
+        err = s.double() - S
+        rse_sd = torch.sqrt(torch.clamp(n * S2 - S * S, min=0) / L)
+        study.append({"L": L, "ace_rel_rmse": float(torch.sqrt((err ** 2).mean()) / S.mean()),
+                      "ace_mean_rel_bias": float(err.mean() / S.mean()),
+                      "rse_rel_sd": float(torch.sqrt((rse_sd ** 2).mean()) / S.mean())})
+    out["estimator_study"] = study
+    out["S_mean"] = float(S.mean())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +378,9 @@ def main():
         torch.cuda.empty_cache()
         extra["heavy_tail_4096"] = heavy_tail_runs(max(2, args.steps // 8))
         extra["serving_256"] = serving_runs()
+        log("exact S(q, D) and estimator study")
+        extra["exact_score_connection_log"] = exact_score_runs(X, W, K)
+        log(f"  {extra['exact_score_connection_log']['ms_per_launch']:.3f} ms per launch")
 
     base = None
     if not args.no_cpu_baseline:

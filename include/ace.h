@@ -196,6 +196,17 @@ ace_status ace_get_counters(ace_ctx ctx, ace_counters* out);
  * if a count is negative or a table does not sum to n.  Synchronises the device. */
 ace_status ace_set_counts(ace_ctx ctx, const int32_t* counts_host, int64_t n);
 
+/* Exact target of the estimator (Sec. 3, Eq. thescore), independent of any context:
+ *   S_dev[a] = sum_i p(q_a, x_i)^K,  p = 1 - arccos(q.x / (|q||x|)) / pi  (Eq. srp),
+ * with p = 1 when q and x are both zero and 1/2 when exactly one is.  S2_dev (may be NULL)
+ * receives sum_i p^{2K}, from which the variance of estimating S by uniform sampling
+ * follows.  Q_dev FP32 [m][d], X_dev FP32 [n][d], S_dev / S2_dev FP64 [m], all device
+ * memory on `device`, owned by the caller.  Inner products and norms are FP64 sums of the
+ * exact products; the per-point terms are added in an unspecified order.  1 <= K <= 64;
+ * m = 0 is a no-op, n = 0 gives zeros.  Stream-ordered. */
+ace_status ace_exact_score(const float* Q_dev, int64_t m, const float* X_dev, int64_t n, int32_t d, int32_t K,
+                           double* S_dev, double* S2_dev, int32_t device, void* stream);
+
 /* Per-kernel timing of a context, from HIP events recorded on the launch stream around
  * every kernel launch while profiling is on. */
 typedef struct {

@@ -31,7 +31,7 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
-           "ace_server_destroy"]
+           "ace_server_destroy", "ace_exact_score"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH):
         "ace_server_get_stats": [P, ctypes.POINTER(ServerStats)],
         "ace_server_reset_stats": [P],
         "ace_server_destroy": [P],
+        "ace_exact_score": [P, i64, P, i64, i32, i32, P, P, i32, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -308,6 +309,23 @@ class ACE:
     def set_counts(self, counts: np.ndarray, n: int):
         counts = np.ascontiguousarray(counts, np.int32)
         _check(self.lib.ace_set_counts(self.h, counts.ctypes.data_as(ctypes.c_void_p), int(n)), "ace_set_counts")
+
+
+def exact_score(Q, X, K: int, want_S2: bool = False, stream=None):
+    """S(q, D) = sum_x p(q, x)^K for every row q of Q against the rows of X (Eq. thescore),
+    on the GPU.  Q, X: contiguous float32 CUDA tensors [m][d], [n][d].  Returns FP64 S
+    (and sum p^{2K} when want_S2)."""
+    import torch
+    lib = load_library()
+    if Q.dim() != 2 or X.dim() != 2 or Q.shape[1] != X.shape[1]:
+        raise ValueError("Q and X must be [m][d] and [n][d]")
+    m, d = Q.shape
+    S = torch.empty(m, dtype=torch.float64, device=Q.device)
+    S2 = torch.empty(m, dtype=torch.float64, device=Q.device) if want_S2 else None
+    _check(lib.ace_exact_score(_dev_ptr(Q, torch.float32, "Q"), m, _dev_ptr(X, torch.float32, "X"), X.shape[0], d,
+                               int(K), S.data_ptr(), S2.data_ptr() if S2 is not None else None,
+                               Q.device.index or 0, _stream_ptr(stream)), "ace_exact_score")
+    return (S, S2) if want_S2 else S
 
 
 def _host_ptr(a, dtype, what: str):

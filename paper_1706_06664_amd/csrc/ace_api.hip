@@ -760,6 +760,28 @@ ace_status ace_get_counters(ace_ctx c, ace_counters* out) {
     return ACE_OK;
 }
 
+ace_status ace_exact_score(const float* Q, int64_t m, const float* X, int64_t n, int32_t d, int32_t K, double* S,
+                           double* S2, int32_t device, void* stream) {
+    if (m < 0 || n < 0 || d < 1 || K < 1 || K > 64 || device < 0) return ACE_E_INVALID;
+    if (m > 0 && (!Q || !S)) return ACE_E_INVALID;
+    if (n > 0 && !X) return ACE_E_INVALID;
+    if ((int64_t)d > (int64_t)1 << 24) return ACE_E_INVALID;
+    if (m == 0) return ACE_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+        (void)hipGetLastError();
+        return ACE_E_DEVICE;
+    }
+    DeviceGuard g(device);
+    if (!g.ok) return ACE_E_DEVICE;
+    hipError_t e = launch_exact_score(Q, m, X, n, d, K, S, S2, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return ACE_E_DEVICE;
+    }
+    return ACE_OK;
+}
+
 ace_status ace_set_counts(ace_ctx c, const int32_t* host, int64_t n) {
     ace_status st = enter(c);
     if (st) return st;

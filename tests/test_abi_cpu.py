@@ -102,3 +102,13 @@ def test_request_record_layout_matches_header():
         [0, 4, 8, 16, 24, 32]
     assert ctypes.sizeof(ServerConfig) == 24
     assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16
+
+
+def test_exact_score_rejects_bad_arguments():
+    lib = _lib()
+    S = ctypes.c_double()
+    assert lib.ace_exact_score(None, 1, None, 1, 4, 3, ctypes.byref(S), None, 0, None) == 1   # NULL Q
+    assert lib.ace_exact_score(None, 0, None, 0, 4, 3, None, None, 0, None) == 0              # m = 0: no-op
+    assert lib.ace_exact_score(None, 0, None, 0, 4, 65, None, None, 0, None) == 1             # K > 64
+    assert lib.ace_exact_score(None, 0, None, 0, 0, 3, None, None, 0, None) == 1              # d = 0
+    assert lib.ace_exact_score(None, -1, None, 0, 4, 3, None, None, 0, None) == 1             # m < 0
