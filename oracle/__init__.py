@@ -39,6 +39,8 @@ def _load():
     lib.ace_oracle_project.argtypes = [P, i64, i32, P, i32, P, P]
     lib.ace_oracle_hash.argtypes = [P, i64, i32, P, i32, i32, P, P]
     lib.ace_oracle_insert.argtypes = [P, i64, i32, i32, P, P, P, P]
+    lib.ace_oracle_insert_capped.argtypes = [P, i64, i32, i32, i64, P, P, P, P]
+    lib.ace_oracle_insert_capped.restype = i64
     lib.ace_oracle_delete.argtypes = [P, i64, i32, i32, P, P, P, P]
     lib.ace_oracle_delete.restype = i64
     lib.ace_oracle_score.argtypes = [P, i64, i32, i32, P, P]
@@ -111,8 +113,11 @@ def exact_score(Q, X, K: int):
 class Sketch:
     """L count arrays of 2^K entries with the running statistics (Alg. 1, Sec. 3.4.1)."""
 
-    def __init__(self, K: int, L: int):
-        self.K, self.L = K, L
+    def __init__(self, K: int, L: int, cap: int | None = None):
+        """cap: saturating counters that stop at `cap` (Sec. 3.4's short counters use 65535
+        for 16 bits); None: unbounded counts."""
+        self.K, self.L, self.cap = K, L, cap
+        self.dropped = 0
         self.counts = np.zeros((L, 1 << K), np.int64)
         self.S2 = np.zeros(L, np.int64)
         self.S3 = np.zeros((L, 2), np.uint64)
@@ -124,8 +129,13 @@ class Sketch:
     def insert_codes(self, codes):
         codes = np.ascontiguousarray(codes, np.uint16)
         assert codes.ndim == 2 and codes.shape[1] == self.L
-        _load().ace_oracle_insert(_ptr(codes), codes.shape[0], self.K, self.L, _ptr(self.counts),
-                                  _ptr(self.S2), _ptr(self.S3), _ptr(self.n))
+        if self.cap is None:
+            _load().ace_oracle_insert(_ptr(codes), codes.shape[0], self.K, self.L, _ptr(self.counts),
+                                      _ptr(self.S2), _ptr(self.S3), _ptr(self.n))
+        else:
+            self.dropped += int(_load().ace_oracle_insert_capped(_ptr(codes), codes.shape[0], self.K, self.L,
+                                                                 int(self.cap), _ptr(self.counts), _ptr(self.S2),
+                                                                 _ptr(self.S3), _ptr(self.n)))
 
     def delete_codes(self, codes) -> int:
         codes = np.ascontiguousarray(codes, np.uint16)

@@ -135,6 +135,37 @@ void ace_oracle_insert(const uint16_t* codes, int64_t n, int32_t K, int32_t L,
 }
 
 /*
+ * Short counters (Sec. 3.4 keeps each count in a 16-bit integer).  With a cap, a count
+ * that already equals the cap keeps its value and the increment is dropped (a saturating
+ * counter).  S2 and S3 follow the stored counts, so sum_j S2_j / (n L) is the mean of the
+ * stored-count scores of the inserted points.  Returns the number of dropped increments.
+ * Inserting only, the stored count of a bucket is min(true count, cap) in any order.
+ */
+int64_t ace_oracle_insert_capped(const uint16_t* codes, int64_t n, int32_t K, int32_t L, int64_t cap,
+                                 int64_t* counts, int64_t* S2, uint64_t* S3, int64_t* n_total) {
+    const int64_t B = (int64_t)1 << K;
+    int64_t dropped = 0;
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t j = 0; j < L; j++) {
+            int64_t* a = &counts[j * B + codes[i * L + j]];
+            if (*a >= cap) {
+                dropped++;
+                continue;
+            }
+            const int64_t before = *a, after = before + 1;
+            S2[j] += after * after - before * before;
+            u128 cube = ((u128)S3[2 * j + 1] << 64) | S3[2 * j];
+            cube += (u128)(after * after * after - before * before * before);
+            S3[2 * j] = (uint64_t)cube;
+            S3[2 * j + 1] = (uint64_t)(cube >> 64);
+            *a = after;
+        }
+        *n_total += 1;
+    }
+    return dropped;
+}
+
+/*
  * Deletion (Sec. 3.4.1, Eq. dynsub): decrement each table's count, S2 shrinks
  * by c^2 - (c-1)^2 = 2c-1 with c the count before the decrement.  A point
  * whose bucket is empty in some table cannot have been inserted; such a point

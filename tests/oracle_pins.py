@@ -18,6 +18,9 @@ What pins what (arXiv 1706.06664):
   collision_law        - Monte Carlo SRP collision rate vs 1 - theta/pi (Eq. srp, Eq. metasrp)
   unbiased             - mean over many tables of A_j[H_j(q)] vs sum_i p_i^K (Theorem 1)
   table_sigma_bound    - the per-table sigma bounds the inserted points' sigma
+  saturating_counters  - short counters (Sec. 3.4) with a cap: stored counts equal
+                         min(true count, cap) in any insertion order, S2/S3 follow
+                         them, dropped increments = sum of the excess
 """
 from __future__ import annotations
 
@@ -329,12 +332,44 @@ def table_sigma_bound(seed: int = 21):
     assert abs(np.mean(per) - th["sigma_table"]) <= 1e-9 * th["sigma_table"]
 
 
+def saturating_counters(seed: int = 22):
+    rng = np.random.default_rng(seed)
+    K, L, n, cap = 3, 4, 300, 7
+    # skewed codes so that several buckets pass the cap
+    codes = np.minimum(rng.geometric(0.35, size=(n, L)) - 1, (1 << K) - 1).astype(np.uint16)
+    sk = oracle.Sketch(K, L, cap=cap)
+    sk.insert_codes(codes[:120])
+    sk.insert_codes(codes[120:])
+    true = np.stack([np.bincount(codes[:, j].astype(np.int64), minlength=1 << K) for j in range(L)])
+    want = np.minimum(true, cap)
+    assert (true > cap).any()
+    assert np.array_equal(sk.counts, want)
+    assert sk.dropped == int(np.maximum(true - cap, 0).sum())
+    assert int(sk.n[0]) == n
+    assert np.array_equal(sk.S2, (want ** 2).sum(axis=1))
+    assert sk.s3_int == [int((want[j].astype(object) ** 3).sum()) for j in range(L)]
+    # another order gives the same state
+    sk2 = oracle.Sketch(K, L, cap=cap)
+    sk2.insert_codes(codes[rng.permutation(n)])
+    assert np.array_equal(sk2.counts, sk.counts) and np.array_equal(sk2.S2, sk.S2) and sk2.dropped == sk.dropped
+    # a cap that is never reached changes nothing
+    big = oracle.Sketch(K, L, cap=10 ** 9)
+    big.insert_codes(codes)
+    ref = oracle.Sketch(K, L)
+    ref.insert_codes(codes)
+    assert np.array_equal(big.counts, ref.counts) and np.array_equal(big.S2, ref.S2) and big.dropped == 0
+    assert big.s3_int == ref.s3_int
+    # scores read the stored counts
+    T = sk.score_codes(codes[:5], accumulate=False)
+    assert list(T) == [int(sum(want[j, codes[i, j]] for j in range(L))) for i in range(5)]
+
+
 def _clusters(rng, n, d):
     means = rng.standard_normal((3, d)) * 5
     X = means[rng.integers(0, 3, n)] + rng.standard_normal((n, d))
     return X.astype(np.float32), None
 
 
-ALL = [hand_examples, const_mode_is_non_strict, exact_signs, scale_negation, recount,
+ALL = [saturating_counters, hand_examples, const_mode_is_non_strict, exact_signs, scale_negation, recount,
        identical_points, mean_closed_form, order_invariance, sigma_two_pass, deletion,
        collision_law, unbiased, table_sigma_bound]

@@ -28,6 +28,9 @@ MUTANTS = [
     ("margin_too_small", "return (double)n * u / (1.0 - (double)n * u);", "return u / 1024.0;"),
     ("delete_wrong_sign", "S2[j] -= 2 * c - 1;", "S2[j] -= 2 * c + 1;"),
     ("cube_term_dropped", "s3 += (u128)(3 * c * c + 3 * c + 1);", "s3 += (u128)(3 * c * c + 1);"),
+    ("cap_one_too_high", "if (*a >= cap) {", "if (*a > cap) {"),
+    ("capped_cube_uses_square", "cube += (u128)(after * after * after - before * before * before);",
+     "cube += (u128)(after * after - before * before);"),
     ("mean_divides_by_n_only", "out->mu = n > 0 ? (double)s2tot / ((double)n * (double)L) : 0.0;",
      "out->mu = n > 0 ? (double)s2tot / ((double)n) : 0.0;"),
 ]
