@@ -78,7 +78,7 @@ def cpu_baseline(X, W, K, L, target_s=12.0):
                       f"hash+score+threshold+flags, {t2:.1f} s on {threads} OpenMP threads"}
 
 
-def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None):
+def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, counter_bits=32):
     """Time `steps` full steps; return timing, per-kernel event timing and counters.
     If `keep` is a dict, the last step's T (int32, device) is stored in keep["T"]."""
     import torch
@@ -86,7 +86,7 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None):
     n, d = Xd.shape
     s = torch.empty(n, dtype=torch.float32, device=Xd.device)
     T = torch.empty(n, dtype=torch.int32, device=Xd.device)
-    ace = ACE(W, K, L, precision=precision, device=0, refine=refine)
+    ace = ACE(W, K, L, precision=precision, device=0, refine=refine, counter_bits=counter_bits)
 
     def step():
         ace.reset()
@@ -132,6 +132,7 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None):
         "refined_bit_frac": (c1["bits_refined"] - c0["bits_refined"]) / max(1, bits),
         "raw_flip_rate": (c1["bits_flipped"] - c0["bits_flipped"]) / max(1, bits),
         "in_bound_unrefined_frac": (c1["bits_in_bound_unrefined"] - c0["bits_in_bound_unrefined"]) / max(1, bits),
+        "saturated_increments_last_step": c1["saturated_increments"],
         "flagged": int(flags.sum().item()), "tau": th["tau"],
     }
 
@@ -360,6 +361,10 @@ def main():
         extra["connection_log_bf16"] = b
         extra["connection_log_bf16_speedup"] = head["ms_per_step"] / b["ms_per_step"]
         log(f"  {b['ms_per_step']:.3f} ms/step")
+        log("connection-log fp32, 16-bit counters")
+        c16 = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup, counter_bits=16)
+        extra["connection_log_counters16"] = c16
+        log(f"  {c16['ms_per_step']:.3f} ms/step, {c16['saturated_increments_last_step']} saturated increments")
         del Xd
         torch.cuda.empty_cache()
         n3, d3, K3, L3 = args.low_rank_n, 1024, 15, 64

@@ -96,7 +96,11 @@ typedef struct {
     int64_t max_batch_rows;  /* rows hashed per internal chunk; 0 = 1<<20 */
     int64_t mem_budget;      /* device bytes the context may allocate; 0 = unlimited */
     int32_t bound_model;     /* ace_bound_model */
-    int32_t reserved;        /* must be 0 */
+    int32_t counter_bits;    /* 0 or 32: int32 counts.  16: uint16 counts (the short counters of
+                                Sec. 3.4, half the memory) that saturate at 65535: an increment
+                                of a full count is dropped and counted (saturated_increments), S2
+                                and S3 follow the stored counts, a decrement below zero is clamped
+                                and reported as ACE_E_STATE */
 } ace_config;
 
 /* Result of ace_threshold (all scores are s = T / L). */
@@ -123,10 +127,12 @@ typedef struct {
     uint64_t bits_refined;   /* bits recomputed in FP64 */
     uint64_t bits_flipped;   /* refined bits whose sign differed from the low-precision sign */
     uint64_t bits_in_bound_unrefined;  /* refine = 2: bits inside the bound, left raw */
+    uint64_t saturated_increments;     /* 16-bit counters: increments dropped at 65535 since the
+                                          last reset */
 } ace_counters;
 
 /* Create a context on cfg->device: copies W (host, FP32 [d][K*L]) and zeroes the L x 2^K
- * int32 counts.  Returns ACE_E_INVALID for out-of-range fields or NULL pointers,
+ * counts (int32, or uint16 with counter_bits = 16).  Returns ACE_E_INVALID for out-of-range fields or NULL pointers,
  * ACE_E_NOMEM if allocation fails or exceeds cfg->mem_budget, ACE_E_DEVICE if the
  * device cannot be used.  *out is set only on success. */
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out);
@@ -181,7 +187,8 @@ ace_status ace_insert_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, v
 ace_status ace_score_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, float* s_dev,
                            uint32_t* T_dev, void* stream);
 
-/* Copy the counts to the host: int32 [L][2^K].  Synchronises the device. */
+/* Copy the counts to the host: int32 [L][2^K] (16-bit counts are widened).  Synchronises
+ * the device. */
 ace_status ace_get_counts(ace_ctx ctx, int32_t* counts_host);
 
 /* Copy the exact per-table sums to the host: S2 int64 [L], S3 uint64 [L][2] (lo, hi of an
@@ -193,7 +200,8 @@ ace_status ace_get_counters(ace_ctx ctx, ace_counters* out);
 
 /* Restore a saved state: counts int32 [L][2^K] (host) describing n inserted points.  S2 and
  * S3 are recomputed from the counts on the device; the scored set is cleared.  ACE_E_INVALID
- * if a count is negative or a table does not sum to n.  Synchronises the device. */
+ * if a count is negative, a table does not sum to n (with 16-bit counters: a count exceeds
+ * 65535 or a table sums to more than n).  Synchronises the device. */
 ace_status ace_set_counts(ace_ctx ctx, const int32_t* counts_host, int64_t n);
 
 /* Exact target of the estimator (Sec. 3, Eq. thescore), independent of any context:

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("max_batch_rows", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
-                ("bound_model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bound_model", ctypes.c_int32), ("counter_bits", ctypes.c_int32)]
 
 
 class Thresh(ctypes.Structure):
@@ -74,7 +74,7 @@ class Counters(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m_scored", ctypes.c_int64), ("sum_T", ctypes.c_int64),
                 ("sum_T2_lo", ctypes.c_uint64), ("sum_T2_hi", ctypes.c_uint64), ("bits_hashed", ctypes.c_uint64),
                 ("bits_refined", ctypes.c_uint64), ("bits_flipped", ctypes.c_uint64),
-                ("bits_in_bound_unrefined", ctypes.c_uint64)]
+                ("bits_in_bound_unrefined", ctypes.c_uint64), ("saturated_increments", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -173,7 +173,8 @@ class ACE:
     """L count arrays of 2^K counters on one GPU, filled and queried through the C ABI."""
 
     def __init__(self, W: np.ndarray, K: int, L: int, precision: str = "fp32", refine: bool = True,
-                 device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0, bound: str = "measured"):
+                 device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0, bound: str = "measured",
+                 counter_bits: int = 32):
         import torch
         W = np.ascontiguousarray(W, dtype=np.float32)
         if W.ndim != 2 or W.shape[1] != K * L:
@@ -183,7 +184,7 @@ class ACE:
         self.device = torch.device("cuda", device)
         rmode = int(refine) if not isinstance(refine, bool) else (1 if refine else 0)
         cfg = Config(self.d, self.K, self.L, _PREC[precision], rmode, device, max_batch_rows,
-                     mem_budget, _BOUND[bound], 0)
+                     mem_budget, _BOUND[bound], int(counter_bits))
         h = ctypes.c_void_p()
         _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
                "ace_create")

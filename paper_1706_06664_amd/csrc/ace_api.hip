@@ -298,8 +298,8 @@ ace_status update_rows(ace_ctx c, const float* X, int64_t n, int sign, hipStream
         if (st != ACE_OK) return st;
         {
             Bracket br(c, s, CLS_UPDATE, m);
-            st = check(c, launch_count_update(c->ws.codes, m, m, c->cfg.K, c->cfg.L, sign, c->counts, c->S2, c->S3,
-                                              c->err, s));
+            st = check(c, launch_count_update(c->ws.codes, m, m, c->cfg.K, c->cfg.L, sign, c->counts, c->cbits, c->S2,
+                                              c->S3, c->err, c->rcnt + 3, s));
         }
         if (st != ACE_OK) return st;
     }
@@ -333,7 +333,7 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     if (cfg->refine < 0 || cfg->refine > 2) return ACE_E_INVALID;
     if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
     if (cfg->bound_model != ACE_BOUND_MEASURED && cfg->bound_model != ACE_BOUND_GENERIC) return ACE_E_INVALID;
-    if (cfg->reserved != 0) return ACE_E_INVALID;
+    if (cfg->counter_bits != 0 && cfg->counter_bits != 16 && cfg->counter_bits != 32) return ACE_E_INVALID;
     if ((int64_t)cfg->d > (int64_t)1 << 24) return ACE_E_INVALID;
 
     int ndev = 0;
@@ -387,7 +387,8 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
         st = st ? st : dev_alloc(c, (void**)&c->Wl, sizeof(uint16_t) * (size_t)c->NP * c->DP);
         st = st ? st : dev_alloc(c, (void**)&c->wbA, sizeof(float) * 4 * (size_t)c->NP);
     }
-    st = st ? st : dev_alloc(c, (void**)&c->counts, sizeof(int32_t) * (size_t)L * B);
+    c->cbits = cfg->counter_bits == 16 ? 16 : 32;
+    st = st ? st : dev_alloc(c, (void**)&c->counts, (size_t)(c->cbits / 8) * (size_t)L * B);
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->mom, sizeof(u64) * 4);
@@ -499,7 +500,7 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     }
     if (e == hipSuccess) e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->wb, wb.data(), wb.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(c->counts, 0, sizeof(int32_t) * (size_t)L * B);
+    if (e == hipSuccess) e = hipMemset(c->counts, 0, (size_t)(c->cbits / 8) * (size_t)L * B);
     if (e == hipSuccess) e = hipMemset(c->S2, 0, sizeof(u64) * (size_t)L);
     if (e == hipSuccess) e = hipMemset(c->S3, 0, sizeof(u64) * 2 * (size_t)L);
     if (e == hipSuccess) e = hipMemset(c->mom, 0, sizeof(u64) * 4);
@@ -533,8 +534,9 @@ ace_status ace_reset(ace_ctx c, void* stream) {
     DeviceGuard g(c->cfg.device);
     hipStream_t s = (hipStream_t)stream;
     Bracket br(c, s, CLS_OTHER);
-    const size_t cb = sizeof(int32_t) * (size_t)c->cfg.L << c->cfg.K;
+    const size_t cb = (size_t)(c->cbits / 8) * (size_t)c->cfg.L << c->cfg.K;
     st = check(c, launch_zero(c->counts, cb, s));
+    if (!st) st = check(c, launch_zero(c->rcnt + 3, sizeof(u64), s));
     if (!st) st = check(c, launch_zero(c->S2, sizeof(u64) * (size_t)c->cfg.L, s));
     if (!st) st = check(c, launch_zero(c->S3, sizeof(u64) * 2 * (size_t)c->cfg.L, s));
     if (!st) st = check(c, launch_zero(c->mom, sizeof(u64) * 4, s));
@@ -584,15 +586,16 @@ ace_status ace_insert_codes(ace_ctx c, const uint16_t* codes, int64_t n, void* s
     if (c->n_total + n > c->cap) return ACE_E_OVERFLOW;
     if (take_injected_failure(c)) return ACE_E_DEVICE;
     DeviceGuard g(c->cfg.device);
-    st = check(c, launch_count_update(codes, n, n, c->cfg.K, c->cfg.L, +1, c->counts, c->S2, c->S3, c->err,
+    st = check(c, launch_count_update(codes, n, n, c->cfg.K, c->cfg.L, +1, c->counts, c->cbits, c->S2, c->S3, c->err,
+                                      c->rcnt + 3,
                                       (hipStream_t)stream));
     if (!st) c->n_total += n;
     return st;
 }
 
 static ace_status score_guard(ace_ctx c) {
-    // T = sum of L counts, each <= n_total, must fit uint32.
-    if ((u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull) return ACE_E_OVERFLOW;
+    // T = sum of L counts, each <= n_total (and <= 65535 with 16-bit counters), must fit uint32.
+    if (c->cbits == 32 && (u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull) return ACE_E_OVERFLOW;
     return ACE_OK;
 }
 
@@ -611,8 +614,8 @@ ace_status ace_score(ace_ctx c, const float* X, int64_t n, float* s_out, uint32_
         if (st) return st;
         {
             Bracket br(c, s, CLS_SCORE, m);
-            st = check(c, launch_score(c->ws.codes, m, m, c->cfg.K, c->cfg.L, c->counts, s_out ? s_out + r0 : nullptr,
-                                       T_out ? T_out + r0 : nullptr, c->mom, s));
+            st = check(c, launch_score(c->ws.codes, m, m, c->cfg.K, c->cfg.L, c->counts, c->cbits,
+                                       s_out ? s_out + r0 : nullptr, T_out ? T_out + r0 : nullptr, c->mom, s));
         }
         if (st) return st;
     }
@@ -628,7 +631,7 @@ ace_status ace_score_codes(ace_ctx c, const uint16_t* codes, int64_t n, float* s
     if ((st = score_guard(c))) return st;
     if (take_injected_failure(c)) return ACE_E_DEVICE;
     DeviceGuard g(c->cfg.device);
-    return check(c, launch_score(codes, n, n, c->cfg.K, c->cfg.L, c->counts, s_out, T_out, c->mom,
+    return check(c, launch_score(codes, n, n, c->cfg.K, c->cfg.L, c->counts, c->cbits, s_out, T_out, c->mom,
                                  (hipStream_t)stream));
 }
 
@@ -724,7 +727,13 @@ ace_status ace_get_counts(ace_ctx c, int32_t* host) {
     if (!host) return ACE_E_INVALID;
     DeviceGuard g(c->cfg.device);
     if ((st = sync_and_check(c))) return st;
-    return check(c, hipMemcpy(host, c->counts, sizeof(int32_t) * ((size_t)c->cfg.L << c->cfg.K), hipMemcpyDeviceToHost));
+    const size_t cnt = (size_t)c->cfg.L << c->cfg.K;
+    if (c->cbits == 32) return check(c, hipMemcpy(host, c->counts, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    std::vector<uint16_t> tmp(cnt);
+    st = check(c, hipMemcpy(tmp.data(), c->counts, sizeof(uint16_t) * cnt, hipMemcpyDeviceToHost));
+    if (!st)
+        for (size_t i = 0; i < cnt; ++i) host[i] = tmp[i];
+    return st;
 }
 
 ace_status ace_get_table_stats(ace_ctx c, int64_t* S2_host, uint64_t* S3_host) {
@@ -757,6 +766,7 @@ ace_status ace_get_counters(ace_ctx c, ace_counters* out) {
     out->bits_refined = r[0];
     out->bits_flipped = r[1];
     out->bits_in_bound_unrefined = r[2];
+    out->saturated_increments = r[3];
     return ACE_OK;
 }
 
@@ -787,18 +797,26 @@ ace_status ace_set_counts(ace_ctx c, const int32_t* host, int64_t n) {
     if (st) return st;
     if (!host || n < 0 || n > c->cap) return ACE_E_INVALID;
     const int64_t B = (int64_t)1 << c->cfg.K;
+    const int32_t top = c->cbits == 16 ? 65535 : INT32_MAX;
     for (int j = 0; j < c->cfg.L; ++j) {
         int64_t sum = 0;
         for (int64_t b = 0; b < B; ++b) {
-            if (host[(int64_t)j * B + b] < 0) return ACE_E_INVALID;
+            if (host[(int64_t)j * B + b] < 0 || host[(int64_t)j * B + b] > top) return ACE_E_INVALID;
             sum += host[(int64_t)j * B + b];
         }
-        if (sum != n) return ACE_E_INVALID;
+        // saturated 16-bit counts may sum to less than n (dropped increments)
+        if (c->cbits == 32 ? sum != n : sum > n) return ACE_E_INVALID;
     }
     DeviceGuard g(c->cfg.device);
     if ((st = sync_and_check(c))) return st;
-    st = check(c, hipMemcpy(c->counts, host, sizeof(int32_t) * (size_t)c->cfg.L * B, hipMemcpyHostToDevice));
-    if (!st) st = check(c, launch_table_sums(c->counts, c->cfg.K, c->cfg.L, c->S2, c->S3, nullptr));
+    if (c->cbits == 32) {
+        st = check(c, hipMemcpy(c->counts, host, sizeof(int32_t) * (size_t)c->cfg.L * B, hipMemcpyHostToDevice));
+    } else {
+        std::vector<uint16_t> tmp((size_t)c->cfg.L * B);
+        for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (uint16_t)host[i];
+        st = check(c, hipMemcpy(c->counts, tmp.data(), sizeof(uint16_t) * tmp.size(), hipMemcpyHostToDevice));
+    }
+    if (!st) st = check(c, launch_table_sums(c->counts, c->cbits, c->cfg.K, c->cfg.L, c->S2, c->S3, nullptr));
     if (!st) st = check(c, launch_zero(c->mom, sizeof(u64) * 4, nullptr));
     if (!st) st = check(c, hipDeviceSynchronize());
     if (!st) c->n_total = n;

@@ -39,11 +39,13 @@ struct ace_ctx_s {
     uint16_t* Wh = nullptr;  // [NP][DP] split-BF16 hi / lo (BF16 precision)
     uint16_t* Wl = nullptr;
     float* wbA = nullptr;    // [4][NP] BF16 bound factors (A, B, C, absolute)
-    int32_t* counts = nullptr;   // [L][2^K]
+    void* counts = nullptr;      // [L][2^K]: int32, or uint16 with 16-bit counters
+    int cbits = 32;              // counter width (32 or 16)
     ace::u64* S2 = nullptr;           // [L]
     ace::u64* S3 = nullptr;           // [L][2]
     ace::u64* mom = nullptr;          // m, sum T, sum T^2 lo, hi
-    ace::u64* rcnt = nullptr;         // bits refined, bits flipped
+    ace::u64* rcnt = nullptr;         // bits refined, bits flipped, bits inside the bound left unrefined,
+                                      // increments dropped by saturated 16-bit counters
     unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
     ace::DevThresh* thr = nullptr;
     ace::Workspace ws;             // workspace of the stream-ordered calls

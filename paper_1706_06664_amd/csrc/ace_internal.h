@@ -90,14 +90,17 @@ hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec
 hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
 // sign = +1 insert, -1 delete
+// counts: int32 [L][2^K] (counter_bits 32) or uint16 [L][2^K] (counter_bits 16, saturating;
+// dropped increments are added to *drops).
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
-                               int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s);
-hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const int32_t* counts,
-                        float* s_out, uint32_t* T_out, u64* mom, hipStream_t s);
+                               void* counts, int counter_bits, u64* S2, u64* S3, unsigned* err, u64* drops,
+                               hipStream_t s);
+hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
+                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s);
 hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode,
                             double alpha, DevThresh* out, hipStream_t s);
 hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);
-hipError_t launch_table_sums(const int32_t* counts, int K, int L, u64* S2, u64* S3, hipStream_t s);
+hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L, u64* S2, u64* S3, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // S[q] = sum_x p(q, x)^K (and S2[q] = sum_x p(q, x)^{2K} when S2 != nullptr); m >= 1.
 hipError_t launch_exact_score(const float* Q, int64_t m, const float* X, int64_t n, int d, int K, double* S,

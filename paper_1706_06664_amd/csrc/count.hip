@@ -1,6 +1,10 @@
 // Count arrays, scores and the threshold (Alg. 1; Sec. 3.4.1 Eq. dynadd / dynsub; Sec. 5.3).
 //
-// Counts are int32 [L][2^K] in device memory.  Alongside them the library keeps
+// Counts are int32 [L][2^K] in device memory, or, with 16-bit counters (the paper's
+// short counters, Sec. 3.4), uint16 [L][2^K] that saturate at 65535: an increment of a
+// full count is dropped (and counted), a decrement below zero is clamped at zero and
+// flagged.  16-bit counts are updated by compare-and-swap on their 32-bit word.
+// Alongside the counts the library keeps
 // S2_j = sum_b A_j[b]^2 (int64) and S3_j = sum_b A_j[b]^3 (unsigned 128-bit, two
 // u64 words), exactly.  An update that moves a count from `old` to `new` adds
 // new^2 - old^2 and new^3 - old^3; atomics return `old`, so the deltas telescope to
@@ -76,14 +80,38 @@ __device__ inline void add128(u64& lo, u64& hi, u64 alo, u64 ahi) {
 
 constexpr int HIST_THREADS = 1024;
 
+// Move the 16-bit count b (inside its 32-bit word) by delta: saturate at 65535 going up,
+// clamp at 0 (and flag) going down.  Returns the stored value before and after.
+__device__ inline void update16(uint32_t* __restrict__ words, int64_t b, int32_t delta, int32_t& before,
+                                int32_t& after, unsigned* __restrict__ err) {
+    uint32_t* w = words + (b >> 1);
+    const int sh = 16 * (int)(b & 1);
+    uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const int32_t o = (int32_t)((cur >> sh) & 0xFFFFu);
+        int32_t nv = o + delta;
+        nv = nv > 65535 ? 65535 : (nv < 0 ? 0 : nv);
+        const uint32_t want = (cur & ~(0xFFFFu << sh)) | ((uint32_t)nv << sh);
+        const uint32_t prev = atomicCAS(w, cur, want);
+        if (prev == cur) {
+            before = o;
+            after = nv;
+            break;
+        }
+        cur = prev;
+    }
+    if (delta < 0 && before + delta < 0) atomicOr(err, 1u);
+}
+
 // LDS-privatised histogram update of one table over a chunk of rows.
 // Grid: (chunks, L).  K <= 15: one uint32 LDS counter per bucket (<= 128 KB).
 // K == 16: two uint16 counters per uint32 word (128 KB), chunk <= 65535 rows.
-template <bool PACK16>
+template <bool PACK16, bool C16>
 __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t* __restrict__ codes, int64_t ldc,
                                                                   int64_t n, int64_t rows_per_block, int K, int sign,
-                                                                  int32_t* __restrict__ counts, u64* __restrict__ S2,
-                                                                  u64* __restrict__ S3, unsigned* __restrict__ err) {
+                                                                  void* __restrict__ counts_v, u64* __restrict__ S2,
+                                                                  u64* __restrict__ S3, unsigned* __restrict__ err,
+                                                                  u64* __restrict__ drops) {
     extern __shared__ uint32_t hist[];
     __shared__ u64 red[3 * (HIST_THREADS / 64)];
     const int j = blockIdx.y;
@@ -103,19 +131,31 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
             atomicAdd(&hist[b], 1u);
     }
     __syncthreads();
-    u64 s2 = 0, s3lo = 0, s3hi = 0;
-    int32_t* cnt = counts + (int64_t)j * B;
+    u64 s2 = 0, s3lo = 0, s3hi = 0, dropped = 0;
     for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
         const uint32_t h = PACK16 ? ((hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu) : hist[b];
         if (h) {
             const int32_t delta = sign > 0 ? (int32_t)h : -(int32_t)h;
-            const int32_t old = atomicAdd(&cnt[b], delta);
-            if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+            int32_t old, moved;
+            if (C16) {
+                int32_t nv;
+                update16(reinterpret_cast<uint32_t*>(counts_v) + (((int64_t)j * B) >> 1), b, delta, old, nv, err);
+                moved = nv - old;
+                if (sign > 0) dropped += (u64)(delta - moved);
+            } else {
+                old = atomicAdd(reinterpret_cast<int32_t*>(counts_v) + (int64_t)j * B + b, delta);
+                if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+                moved = delta;
+            }
             u64 d2, d3lo, d3hi;
-            sq_cube_delta(old, delta, d2, d3lo, d3hi);
+            sq_cube_delta(old, moved, d2, d3lo, d3hi);
             s2 += d2;
             add128(s3lo, s3hi, d3lo, d3hi);
         }
+    }
+    if (C16) {
+        dropped = wave_sum_u64(dropped);
+        if ((threadIdx.x & 63) == 0 && dropped) atomicAdd(drops, dropped);
     }
     block_sum3(s2, s3lo, s3hi, red);
     if (threadIdx.x == 0) {
@@ -126,10 +166,11 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
 
 // Direct update for small batches: one thread per (row, table), one global atomic each.
 // Grid: (ceil(n/256), L).
+template <bool C16>
 __global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __restrict__ codes, int64_t ldc,
-                                                            int64_t n, int K, int sign, int32_t* __restrict__ counts,
+                                                            int64_t n, int K, int sign, void* __restrict__ counts_v,
                                                             u64* __restrict__ S2, u64* __restrict__ S3,
-                                                            unsigned* __restrict__ err) {
+                                                            unsigned* __restrict__ err, u64* __restrict__ drops) {
     __shared__ u64 red[3 * 4];
     const int j = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,9 +178,18 @@ __global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __re
     if (i < n) {
         const uint32_t b = codes[(int64_t)j * ldc + i] & ((1u << K) - 1u);
         const int32_t delta = sign > 0 ? 1 : -1;
-        const int32_t old = atomicAdd(&counts[((int64_t)j << K) + b], delta);
-        if ((int64_t)old + delta < 0) atomicOr(err, 1u);
-        sq_cube_delta(old, delta, s2, s3lo, s3hi);
+        int32_t old, moved;
+        if (C16) {
+            int32_t nv;
+            update16(reinterpret_cast<uint32_t*>(counts_v) + (((int64_t)j << K) >> 1), b, delta, old, nv, err);
+            moved = nv - old;
+            if (sign > 0 && moved == 0) atomicAdd(drops, 1ull);
+        } else {
+            old = atomicAdd(reinterpret_cast<int32_t*>(counts_v) + ((int64_t)j << K) + b, delta);
+            if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+            moved = delta;
+        }
+        sq_cube_delta(old, moved, s2, s3lo, s3hi);
     }
     block_sum3(s2, s3lo, s3hi, red);
     if (threadIdx.x == 0) {
@@ -150,8 +200,9 @@ __global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __re
 
 // Query phase: T(q) = sum_j A_j[H_j(q)], s = T / L; one thread per row.  The block's
 // (m, sum T, sum T^2) are added to the scored-set moments mom[0..3].
+template <typename CT>
 __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__ codes, int64_t ldc, int64_t n,
-                                                    int K, int L, const int32_t* __restrict__ counts,
+                                                    int K, int L, const CT* __restrict__ counts,
                                                     float* __restrict__ s_out, uint32_t* __restrict__ T_out,
                                                     u64* __restrict__ mom) {
     __shared__ u64 red[3 * 4];
@@ -160,7 +211,7 @@ __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__
     const bool ok = i < n;
     if (ok) {
         const uint16_t* c = codes + i;
-        const int32_t* a = counts;
+        const CT* a = counts;
         const uint32_t bm = (1u << K) - 1u;  // codes from callers are reduced to K bits
         int j = 0;
         for (; j + 4 <= L; j += 4) {
@@ -249,7 +300,8 @@ __global__ __launch_bounds__(256) void flags_kernel(const uint32_t* __restrict__
 }
 
 // S2_j and S3_j recomputed from the counts (checkpoint restore).  Grid: L blocks.
-__global__ __launch_bounds__(256) void table_sums_kernel(const int32_t* __restrict__ counts, int K,
+template <typename CT>
+__global__ __launch_bounds__(256) void table_sums_kernel(const CT* __restrict__ counts, int K,
                                                          u64* __restrict__ S2, u64* __restrict__ S3) {
     __shared__ u64 red[3 * 4];
     const int j = blockIdx.x;
@@ -277,23 +329,33 @@ __global__ __launch_bounds__(256) void zero_kernel(uint32_t* __restrict__ p, int
 }  // namespace
 
 hipError_t init_kernel_attributes() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&update_lds_kernel<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&update_lds_kernel<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    const void* fns[] = {reinterpret_cast<const void*>(&update_lds_kernel<false, false>),
+                         reinterpret_cast<const void*>(&update_lds_kernel<true, false>),
+                         reinterpret_cast<const void*>(&update_lds_kernel<false, true>),
+                         reinterpret_cast<const void*>(&update_lds_kernel<true, true>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
-                               int32_t* counts, u64* S2, u64* S3, unsigned* err, hipStream_t s) {
+                               void* counts, int counter_bits, u64* S2, u64* S3, unsigned* err, u64* drops,
+                               hipStream_t s) {
+    const bool c16 = counter_bits == 16;
     if (n <= 0) return hipSuccess;
     const int64_t B = (int64_t)1 << K;
     // The LDS histogram pays one scan of 2^K buckets per block; use it when a block
     // sees at least 2^K / 2 rows, otherwise one global atomic per (row, table).
     if (n < B / 2) {
         const int64_t nb = (n + 255) / 256;
-        hipLaunchKernelGGL(update_direct_kernel, dim3((unsigned)nb, (unsigned)L), dim3(256), 0, s, codes, ldc, n, K,
-                           sign, counts, S2, S3, err);
+        if (c16)
+            hipLaunchKernelGGL(update_direct_kernel<true>, dim3((unsigned)nb, (unsigned)L), dim3(256), 0, s, codes,
+                               ldc, n, K, sign, counts, S2, S3, err, drops);
+        else
+            hipLaunchKernelGGL(update_direct_kernel<false>, dim3((unsigned)nb, (unsigned)L), dim3(256), 0, s, codes,
+                               ldc, n, K, sign, counts, S2, S3, err, drops);
         return hipGetLastError();
     }
     int64_t chunks = (n + B / 2 - 1) / (B / 2);
@@ -306,21 +368,32 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
     }
     chunks = (n + rows - 1) / rows;
     const size_t lds = (size_t)(K == 16 ? (B >> 1) : B) * sizeof(uint32_t);
-    if (K == 16)
-        hipLaunchKernelGGL(update_lds_kernel<true>, dim3((unsigned)chunks, (unsigned)L), dim3(HIST_THREADS), lds, s,
-                           codes, ldc, n, rows, K, sign, counts, S2, S3, err);
+    const dim3 grid((unsigned)chunks, (unsigned)L);
+    if (K == 16 && c16)
+        hipLaunchKernelGGL((update_lds_kernel<true, true>), grid, dim3(HIST_THREADS), lds, s, codes, ldc, n, rows, K,
+                           sign, counts, S2, S3, err, drops);
+    else if (K == 16)
+        hipLaunchKernelGGL((update_lds_kernel<true, false>), grid, dim3(HIST_THREADS), lds, s, codes, ldc, n, rows, K,
+                           sign, counts, S2, S3, err, drops);
+    else if (c16)
+        hipLaunchKernelGGL((update_lds_kernel<false, true>), grid, dim3(HIST_THREADS), lds, s, codes, ldc, n, rows, K,
+                           sign, counts, S2, S3, err, drops);
     else
-        hipLaunchKernelGGL(update_lds_kernel<false>, dim3((unsigned)chunks, (unsigned)L), dim3(HIST_THREADS), lds, s,
-                           codes, ldc, n, rows, K, sign, counts, S2, S3, err);
+        hipLaunchKernelGGL((update_lds_kernel<false, false>), grid, dim3(HIST_THREADS), lds, s, codes, ldc, n, rows,
+                           K, sign, counts, S2, S3, err, drops);
     return hipGetLastError();
 }
 
-hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const int32_t* counts,
-                        float* s_out, uint32_t* T_out, u64* mom, hipStream_t s) {
+hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
+                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + 255) / 256;
-    hipLaunchKernelGGL(score_kernel, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L, counts, s_out, T_out,
-                       mom);
+    if (counter_bits == 16)
+        hipLaunchKernelGGL(score_kernel<uint16_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
+                           reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom);
+    else
+        hipLaunchKernelGGL(score_kernel<int32_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
+                           reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom);
     return hipGetLastError();
 }
 
@@ -338,8 +411,13 @@ hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mod
     return hipGetLastError();
 }
 
-hipError_t launch_table_sums(const int32_t* counts, int K, int L, u64* S2, u64* S3, hipStream_t s) {
-    hipLaunchKernelGGL(table_sums_kernel, dim3((unsigned)L), dim3(256), 0, s, counts, K, S2, S3);
+hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L, u64* S2, u64* S3, hipStream_t s) {
+    if (counter_bits == 16)
+        hipLaunchKernelGGL(table_sums_kernel<uint16_t>, dim3((unsigned)L), dim3(256), 0, s,
+                           reinterpret_cast<const uint16_t*>(counts), K, S2, S3);
+    else
+        hipLaunchKernelGGL(table_sums_kernel<int32_t>, dim3((unsigned)L), dim3(256), 0, s,
+                           reinterpret_cast<const int32_t*>(counts), K, S2, S3);
     return hipGetLastError();
 }
 

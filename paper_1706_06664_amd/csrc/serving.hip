@@ -268,10 +268,11 @@ ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait
         for (; i < sl.reqs.size() && sl.reqs[i].kind == kind; ++i) len += sl.reqs[i].n;
         const uint16_t* codes = sl.ws.codes + off;   // table j of row r at codes[j * rows + r]
         if (kind == ACE_REQ_INSERT)
-            st = check(c, launch_count_update(codes, rows, len, c->cfg.K, c->cfg.L, +1, c->counts, c->S2, c->S3,
-                                              c->err, sl.s));
+            st = check(c, launch_count_update(codes, rows, len, c->cfg.K, c->cfg.L, +1, c->counts, c->cbits, c->S2,
+                                              c->S3, c->err, c->rcnt + 3, sl.s));
         else
-            st = check(c, launch_score(codes, rows, len, c->cfg.K, c->cfg.L, c->counts, sl.sd + off, sl.Td + off,
+            st = check(c, launch_score(codes, rows, len, c->cfg.K, c->cfg.L, c->counts, c->cbits, sl.sd + off,
+                                       sl.Td + off,
                                        c->mom, sl.s));
     }
     st = st ? st : check(c, hipEventRecord(sl.cnt, sl.s));
@@ -419,7 +420,8 @@ ace_status submit_at(ace_server srv, int32_t kind, const float* X, int64_t n, fl
     if (srv->err != ACE_OK) return srv->err;
     // n_total counts every admitted insert, so the guards hold for any interleaving.
     if (kind == ACE_REQ_INSERT && c->n_total + n > c->cap) return ACE_E_OVERFLOW;
-    if (kind == ACE_REQ_SCORE && (u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull) return ACE_E_OVERFLOW;
+    if (kind == ACE_REQ_SCORE && c->cbits == 32 && (u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull)
+        return ACE_E_OVERFLOW;
     if (c->fail_next) {
         c->fail_next = 0;
         srv->err = ACE_E_DEVICE;

@@ -40,7 +40,8 @@ def test_status_strings_and_version():
 
 @pytest.mark.parametrize("field,value", [("d", 0), ("K", 0), ("K", 17), ("L", 0), ("L", 5000),
                                          ("precision", 7), ("refine", 3), ("refine", -1), ("max_batch_rows", -1),
-                                         ("mem_budget", -5), ("device", -1), ("bound_model", 2), ("reserved", 1)])
+                                         ("mem_budget", -5), ("device", -1), ("bound_model", 2), ("counter_bits", 1),
+                                         ("counter_bits", 8), ("counter_bits", 64)])
 def test_create_rejects_bad_config(field, value):
     from paper_1706_06664_amd.ace import Config
     lib = _lib()
