@@ -241,3 +241,15 @@ def serving_trace(n_requests: int, d: int, seed: int = 5, median_batch: int = 25
         rng = np.random.Generator(np.random.PCG64([seed, 7]))
         row0 = (rng.random(n_requests) * (pool_rows - n + 1)).astype(np.int64)
     return kind, n, row0, out0, t, np.ascontiguousarray(pool, np.float32)
+
+
+def structured_signs(d: int, K: int, L: int, seed: int):
+    """Random sign diagonals of the structured projection: returns (signs uint8 [B][3][dp]
+    holding 0 for +1 and 1 for -1, dp), with dp = max(64, next power of two >= d) and
+    B = ceil(K*L / dp) independent blocks of three diagonals each."""
+    dp = 64
+    while dp < d:
+        dp *= 2
+    B = -(-(K * L) // dp)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.random((B, 3, dp)) < 0.5).astype(np.uint8), dp
