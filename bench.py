@@ -78,7 +78,7 @@ def cpu_baseline(X, W, K, L, target_s=12.0):
                       f"hash+score+threshold+flags, {t2:.1f} s on {threads} OpenMP threads"}
 
 
-def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, counter_bits=32):
+def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, counter_bits=32, signs=None):
     """Time `steps` full steps; return timing, per-kernel event timing and counters.
     If `keep` is a dict, the last step's T (int32, device) is stored in keep["T"]."""
     import torch
@@ -86,7 +86,8 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     n, d = Xd.shape
     s = torch.empty(n, dtype=torch.float32, device=Xd.device)
     T = torch.empty(n, dtype=torch.int32, device=Xd.device)
-    ace = ACE(W, K, L, precision=precision, device=0, refine=refine, counter_bits=counter_bits)
+    ace = ACE(W if signs is None else None, K, L, precision=precision, device=0, refine=refine,
+              counter_bits=counter_bits, signs=signs, d=d)
 
     def step():
         ace.reset()
@@ -119,6 +120,8 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     flop = 2.0 * rows * d * K * L
     executed = flop * (16.0 / K) * (3.0 if precision == "bf16" else 1.0)
     kernel = {"fp32": "hash_fp32_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}[precision]
+    if signs is not None:
+        kernel = "hash_struct_kernel"
     ach = flop / (hash_ms / 1e3)
     bits = c1["bits_hashed"] - c0["bits_hashed"]
     return {
@@ -196,6 +199,21 @@ def heavy_tail_runs(steps):
     out["fp8_in_bound_frac"] = out["fp8"]["in_bound_unrefined_frac"]
     out["bf16_speedup"] = out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"]
     out["fp8_raw_speedup"] = out["fp32"]["ms_per_step"] / out["fp8"]["ms_per_step"]
+    # Structured projections (H D3 H D2 H D1, one 4096-point block per row): another hash
+    # family (the paper's fast-transform hashing), refined to the FP64 signs of its own
+    # dense equivalent.
+    from ace_inputs import structured_signs
+    s4, _ = structured_signs(d4, K4, L4, 1706066647)
+    log(f"heavy-tail {n4}x{d4} structured fp32: steps {steps}")
+    st = run_workload(X4, None, K4, L4, "fp32", steps, 1, signs=s4)
+    rows = st["roofline"]["rows_per_launch"]
+    st["roofline"] = {"bound": "hbm", "kernel": "hash_struct_kernel", "avg_launch_ms": st["roofline"]["avg_launch_ms"],
+                      "achieved": 4.0 * d4 * rows / (st["roofline"]["avg_launch_ms"] / 1e3) / 1e9, "peak": 8000.0,
+                      "unit": "GB/s", "adds_per_row": 3 * d4 * 12}
+    st["roofline"]["frac"] = st["roofline"]["achieved"] / 8000.0
+    out["structured_fp32"] = st
+    out["structured_speedup_vs_fp32"] = out["fp32"]["ms_per_step"] / st["ms_per_step"]
+    log(f"  {st['ms_per_step']:.3f} ms/step")
     del X4, c32, c8
     torch.cuda.empty_cache()
     return out
@@ -361,6 +379,11 @@ def main():
         extra["connection_log_bf16"] = b
         extra["connection_log_bf16_speedup"] = head["ms_per_step"] / b["ms_per_step"]
         log(f"  {b['ms_per_step']:.3f} ms/step")
+        from ace_inputs import structured_signs
+        s2, _ = structured_signs(d, K, L, 1706066646)
+        log("connection-log structured fp32")
+        extra["connection_log_structured"] = run_workload(Xd, None, K, L, "fp32", args.steps, args.warmup, signs=s2)
+        log(f"  {extra['connection_log_structured']['ms_per_step']:.3f} ms/step")
         log("connection-log fp32, 16-bit counters")
         c16 = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup, counter_bits=16)
         extra["connection_log_counters16"] = c16

@@ -137,6 +137,18 @@ typedef struct {
  * device cannot be used.  *out is set only on success. */
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out);
 
+/* Create a context whose projections are structured (the fast-transform hashing the paper
+ * costs at O(d log d + K L) per point, Sec. 2.1 / Sec. 3.4) instead of a dense W: bit c of a
+ * row x is the sign of output i = c mod dp of block b = c / dp of
+ *   M_b [x; 0] = H D3_b H D2_b H D1_b [x; 0],
+ * H the dp x dp Sylvester Hadamard matrix (entries +-1), D diagonals of signs,
+ * dp = max(64, next power of two >= d) <= 4096, B = ceil(K L / dp) blocks.
+ * signs: host uint8 [B][3][dp], 0 = +1, 1 = -1, D1 first; copied.  Bits inside the FP32
+ * error bound of the transform are recomputed in FP64 (refine = 1) against the dense
+ * integer matrix M, so they equal the dense oracle's bits for W = M^T.  Only ACE_FP32
+ * precision; other fields as ace_create.  ACE_E_INVALID for d > 4096 or a sign byte > 1. */
+ace_status ace_create_structured(const ace_config* cfg, const uint8_t* signs, ace_ctx* out);
+
 /* Synchronise the device and free everything the context owns.  NULL is a no-op.
  * ACE_E_STATE (nothing freed) while a serving loop is attached (ace_server_create). */
 ace_status ace_destroy(ace_ctx ctx);

@@ -18,22 +18,28 @@ from scipy.linalg import hadamard
 
 
 def structured_matrix(signs: np.ndarray, d: int, K: int, L: int) -> np.ndarray:
-    """W = first d columns of the stacked block matrices M_b, transposed: float32 [d][K L]."""
+    """W = first d columns of the stacked block matrices M_b, transposed: float32 [d][K L].
+
+    The products run in FP64 (a library matmul): every entry of every partial product is
+    an integer of magnitude <= dp^2 <= 2^24 and every partial sum stays below 2^53, so the
+    result is exact whatever the order of the additions."""
     B, three, dp = signs.shape
     assert three == 3 and dp >= d and B * dp >= K * L
     if dp > 4096:
         raise ValueError("entries of M reach dp^2 and must stay exact in FP32 (dp <= 4096)")
-    H = hadamard(dp).astype(np.int64)
+    H = hadamard(dp).astype(np.float64)
+    KL = K * L
     rows = []
     for b in range(B):
-        D = [np.where(signs[b, r] == 1, -1, 1).astype(np.int64) for r in range(3)]
-        # M_b = H D3 H D2 H D1 (diagonal D as a column scaling)
-        M = (H * D[0][None, :])
+        D = [np.where(signs[b, r] == 1, -1.0, 1.0) for r in range(3)]
+        need = min(dp, KL - b * dp)                # outputs of this block that are bits
+        # M_b[:need, :d] = H[:need] D3 H D2 H D1[:, :d]  (diagonal D as a scaling)
+        M = H[:, :d] * D[0][None, :d]
         M = H @ (D[1][:, None] * M)
-        M = H @ (D[2][:, None] * M)
-        rows.append(M[:, :d])
-    M = np.concatenate(rows, axis=0)[: K * L]
-    assert np.abs(M).max() <= 1 << 24
+        M = H[:need] @ (D[2][:, None] * M)
+        rows.append(M)
+    M = np.concatenate(rows, axis=0)
+    assert np.abs(M).max() <= 1 << 24 and np.array_equal(M, np.round(M))
     return np.ascontiguousarray(M.T.astype(np.float32))
 
 

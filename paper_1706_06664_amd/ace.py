@@ -31,7 +31,7 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
-           "ace_server_destroy", "ace_exact_score"]
+           "ace_server_destroy", "ace_exact_score", "ace_create_structured"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "ace_server_reset_stats": [P],
         "ace_server_destroy": [P],
         "ace_exact_score": [P, i64, P, i64, i32, i32, P, P, i32, P],
+        "ace_create_structured": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -172,22 +173,33 @@ def _dev_ptr(t, dtype, what: str):
 class ACE:
     """L count arrays of 2^K counters on one GPU, filled and queried through the C ABI."""
 
-    def __init__(self, W: np.ndarray, K: int, L: int, precision: str = "fp32", refine: bool = True,
+    def __init__(self, W: Optional[np.ndarray], K: int, L: int, precision: str = "fp32", refine: bool = True,
                  device: int = 0, max_batch_rows: int = 0, mem_budget: int = 0, bound: str = "measured",
-                 counter_bits: int = 32):
+                 counter_bits: int = 32, signs: Optional[np.ndarray] = None, d: Optional[int] = None):
+        """W: dense projections float32 [d][K*L]; or W=None with `signs` (uint8 [B][3][dp])
+        and `d` for the structured projection H D3 H D2 H D1."""
         import torch
-        W = np.ascontiguousarray(W, dtype=np.float32)
-        if W.ndim != 2 or W.shape[1] != K * L:
-            raise ValueError("W must be float32 [d][K*L]")
         self.lib = load_library()
-        self.d, self.K, self.L = int(W.shape[0]), int(K), int(L)
+        if W is not None:
+            W = np.ascontiguousarray(W, dtype=np.float32)
+            if W.ndim != 2 or W.shape[1] != K * L:
+                raise ValueError("W must be float32 [d][K*L]")
+            d = int(W.shape[0])
+        elif signs is None or d is None:
+            raise ValueError("give W, or signs and d")
+        self.d, self.K, self.L = int(d), int(K), int(L)
         self.device = torch.device("cuda", device)
         rmode = int(refine) if not isinstance(refine, bool) else (1 if refine else 0)
         cfg = Config(self.d, self.K, self.L, _PREC[precision], rmode, device, max_batch_rows,
                      mem_budget, _BOUND[bound], int(counter_bits))
         h = ctypes.c_void_p()
-        _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
-               "ace_create")
+        if W is not None:
+            _check(self.lib.ace_create(ctypes.byref(cfg), W.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+                   "ace_create")
+        else:
+            sg = np.ascontiguousarray(signs, dtype=np.uint8)
+            _check(self.lib.ace_create_structured(ctypes.byref(cfg), sg.ctypes.data_as(ctypes.c_void_p),
+                                                  ctypes.byref(h)), "ace_create_structured")
         self.h = h
 
     def close(self):

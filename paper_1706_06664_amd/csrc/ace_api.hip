@@ -123,7 +123,8 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr};
+    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr,
+                    c->sgn, c->sgn_lane};
     ws_free(&c->ws);
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -266,6 +267,16 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
         a.rowC = w->rown + 2 * w->rows;
         Bracket br(c, s, CLS_HASH, n);
         st = check(c, launch_hash_bf16(a, c->TW, s));
+    } else if (c->sgn) {
+        a.sgn = c->sgn;
+        a.sgn_lane = c->sgn_lane;
+        a.dp = c->dp;
+        a.nblk = c->nblk;
+        a.rows_per_wave = 4;
+        a.gx = c->gx_struct;
+        a.eps_abs = c->eps_struct;
+        Bracket br(c, s, CLS_HASH, n);
+        st = check(c, launch_hash_struct(a, s));
     } else {
         Bracket br(c, s, CLS_HASH, n);
         st = check(c, launch_hash_fp32(a, c->TW, vec, s));
@@ -325,8 +336,72 @@ const char* ace_status_string(ace_status s) {
 
 const char* ace_version(void) { return "ace-mi355x 0.1 (gfx950)"; }
 
+namespace {
+
+// Transform size and blocks of the structured projection: dp = max(64, next power of two
+// >= d) outputs per block, ceil(K L / dp) blocks.
+void structured_shape(int d, int K, int L, int* dp, int* nblk) {
+    int p = 64;
+    while (p < d) p *= 2;
+    *dp = p;
+    *nblk = (K * L + p - 1) / p;
+}
+
+// Dense equivalent of the structured projection, [d][K L] like a caller's W: row c of
+// M_b = H D3 H D2 H D1 is (D1 H D2 H D3 H e_i)^T (H symmetric, D diagonal), computed with an
+// exact integer fast Walsh-Hadamard transform.  Entries are integers of magnitude <= dp^2.
+void structured_dense(const uint8_t* signs, int d, int K, int L, int dp, std::vector<float>& W) {
+    const int KL = K * L;
+    W.assign((size_t)d * KL, 0.f);
+    std::vector<int64_t> v(dp);
+    auto fwht = [&]() {
+        for (int h = 1; h < dp; h <<= 1)
+            for (int i = 0; i < dp; i += 2 * h)
+                for (int k = i; k < i + h; ++k) {
+                    const int64_t a = v[k], b = v[k + h];
+                    v[k] = a + b;
+                    v[k + h] = a - b;
+                }
+    };
+    for (int c = 0; c < KL; ++c) {
+        const int b = c / dp, i = c % dp;
+        const uint8_t* s1 = signs + ((size_t)b * 3 + 0) * dp;
+        const uint8_t* s2 = s1 + dp;
+        const uint8_t* s3 = s2 + dp;
+        for (int u = 0; u < dp; ++u) v[u] = (__builtin_popcount((unsigned)(i & u)) & 1) ? -1 : 1;   // H e_i
+        for (int u = 0; u < dp; ++u) v[u] = s3[u] ? -v[u] : v[u];
+        fwht();
+        for (int u = 0; u < dp; ++u) v[u] = s2[u] ? -v[u] : v[u];
+        fwht();
+        for (int t = 0; t < d; ++t) W[(size_t)t * KL + c] = (float)(s1[t] ? -v[t] : v[t]);
+    }
+}
+
+ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t* signs, ace_ctx* out);
+
+}  // namespace
+
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) {
     if (!cfg || !W_host || !out) return ACE_E_INVALID;
+    return create_impl(cfg, W_host, nullptr, out);
+}
+
+ace_status ace_create_structured(const ace_config* cfg, const uint8_t* signs, ace_ctx* out) {
+    if (!cfg || !signs || !out) return ACE_E_INVALID;
+    if (cfg->precision != ACE_FP32) return ACE_E_INVALID;
+    if (cfg->d < 1 || cfg->d > 4096 || cfg->K < 1 || cfg->K > 16 || cfg->L < 1 || cfg->L > 4096) return ACE_E_INVALID;
+    int dp, nblk;
+    structured_shape(cfg->d, cfg->K, cfg->L, &dp, &nblk);
+    for (size_t i = 0; i < (size_t)nblk * 3 * dp; ++i)
+        if (signs[i] > 1) return ACE_E_INVALID;
+    std::vector<float> W;
+    structured_dense(signs, cfg->d, cfg->K, cfg->L, dp, W);
+    return create_impl(cfg, W.data(), signs, out);
+}
+
+namespace {
+
+ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t* signs, ace_ctx* out) {
     if (cfg->d < 1 || cfg->K < 1 || cfg->K > 16 || cfg->L < 1 || cfg->L > 4096) return ACE_E_INVALID;
     if (cfg->precision != ACE_FP32 && cfg->precision != ACE_BF16 && cfg->precision != ACE_FP8E4M3)
         return ACE_E_INVALID;
@@ -397,6 +472,18 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
     st = st ? st : ws_alloc(c, &c->ws, c->ws_rows);
     c->list_cap = c->ws.list_alloc;
+    if (signs) {
+        structured_shape(d, K, L, &c->dp, &c->nblk);
+        // dp / 32 words per diagonal, padded so that 64-bit loads of the last word stay inside
+        st = st ? st : dev_alloc(c, (void**)&c->sgn, sizeof(uint32_t) * ((size_t)c->nblk * 3 * (c->dp / 32) + 2));
+        st = st ? st : dev_alloc(c, (void**)&c->sgn_lane, sizeof(u64) * (size_t)c->nblk * 3 * 64);
+        // Bound of the three FP32 transforms: g dp^1.5 |x| (3 + 4g), g = m u (1 + 2u)^m,
+        // u = 2^-24, m = log2 dp (rounded up for the FP32 product with |x|).
+        const double u = ldexp(1.0, -24), m = log2((double)c->dp);
+        const double gg = m * u * pow(1.0 + 2.0 * u, m);
+        c->gx_struct = (float)(gg * pow((double)c->dp, 1.5) * (3.0 + 4.0 * gg) * (1.0 + ldexp(1.0, -16)));
+        c->eps_struct = (float)ldexp(1.0, -90);
+    }
     if (st != ACE_OK) {
         free_all(c);
         delete c;
@@ -498,6 +585,19 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
         e = hipMemcpy(c->Wq, Wq.data(), Wq.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->wbA, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && signs) {
+        std::vector<uint32_t> words((size_t)c->nblk * 3 * (c->dp / 32) + 2, 0u);
+        std::vector<u64> lanes((size_t)c->nblk * 3 * 64, 0ull);
+        for (size_t i = 0; i < (size_t)c->nblk * 3 * c->dp; ++i)
+            if (signs[i]) {
+                words[i >> 5] |= 1u << (i & 31);
+                const size_t diag = i / c->dp, el = i % c->dp;
+                lanes[diag * 64 + (el & 63)] |= 1ull << (el >> 6);
+            }
+        e = hipMemcpy(c->sgn, words.data(), words.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->sgn_lane, lanes.data(), lanes.size() * sizeof(u64), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(c->Wt, Wt.data(), Wt.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->wb, wb.data(), wb.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->counts, 0, (size_t)(c->cbits / 8) * (size_t)L * B);
@@ -516,6 +616,8 @@ ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out) 
     *out = c;
     return ACE_OK;
 }
+
+}  // namespace
 
 ace_status ace_destroy(ace_ctx c) {
     if (!c) return ACE_OK;

@@ -39,6 +39,10 @@ struct ace_ctx_s {
     uint16_t* Wh = nullptr;  // [NP][DP] split-BF16 hi / lo (BF16 precision)
     uint16_t* Wl = nullptr;
     float* wbA = nullptr;    // [4][NP] BF16 bound factors (A, B, C, absolute)
+    uint32_t* sgn = nullptr; // structured projection: sign bits [nblk][3][dp / 32] (null: dense W)
+    ace::u64* sgn_lane = nullptr;   // the same bits lane-major: [nblk][3][64], bit r = element 64 r + lane
+    int dp = 0, nblk = 0;    // structured transform size and blocks
+    float gx_struct = 0.f, eps_struct = 0.f;   // structured bound: gx_struct * |x| + eps_struct
     void* counts = nullptr;      // [L][2^K]: int32, or uint16 with 16-bit counters
     int cbits = 32;              // counter width (32 or 16)
     ace::u64* S2 = nullptr;           // [L]

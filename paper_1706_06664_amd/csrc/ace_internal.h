@@ -55,6 +55,12 @@ struct HashArgs {
     const float* rowC;
     const uint8_t* Xq;     // [n][DP] e4m3 codes of the scaled rows (FP8 kernel)
     const uint8_t* Wq;     // [NP][DP] e4m3 codes of the scaled columns
+    // Structured projection (hash_struct kernel): the bound is gx * ||x|| + eps_abs
+    const uint32_t* sgn;   // [nblk][3][dp / 32] sign bits of D1, D2, D3 (1 = negate)
+    const u64* sgn_lane;   // [nblk][3][64]: bit r of word lane = sign bit of element 64 r + lane
+    int32_t dp;            // transform size, a power of two in 64 .. 4096
+    int32_t nblk;          // blocks of dp outputs
+    int32_t rows_per_wave;
 };
 
 // Arguments of the FP64 pass over the queued projections.
@@ -89,6 +95,8 @@ hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec
                               float* rowB, float norm_up, hipStream_t s);
 hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
+hipError_t launch_hash_struct(const HashArgs& a, hipStream_t s);
+hipError_t init_struct_attributes();
 // sign = +1 insert, -1 delete
 // counts: int32 [L][2^K] (counter_bits 32) or uint16 [L][2^K] (counter_bits 16, saturating;
 // dropped increments are added to *drops).

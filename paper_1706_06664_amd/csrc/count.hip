@@ -337,7 +337,7 @@ hipError_t init_kernel_attributes() {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return init_struct_attributes();
 }
 
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,

@@ -60,8 +60,10 @@ def check_flags(flags_gpu: np.ndarray, flags_ref: np.ndarray, T: np.ndarray, L: 
     return int(band.sum())
 
 
-def full_parity(X: np.ndarray, W: np.ndarray, K: int, L: int, device="cuda", **ace_kwargs) -> dict:
-    """Insert all rows, score all rows, threshold and flag, on both sides; assert the bar."""
+def full_parity(X: np.ndarray, W: np.ndarray, K: int, L: int, device="cuda", signs=None, **ace_kwargs) -> dict:
+    """Insert all rows, score all rows, threshold and flag, on both sides; assert the bar.
+    With `signs`, the GPU context uses the structured projection and W is its dense
+    equivalent (what the oracle hashes with)."""
     import torch
     from paper_1706_06664_amd import ACE, codes_as_uint16
 
@@ -73,7 +75,10 @@ def full_parity(X: np.ndarray, W: np.ndarray, K: int, L: int, device="cuda", **a
     rc, th_o = sk.threshold(oracle.MODE_SCORED, 1.0)
     flags_o = sk.flags(T_o, th_o["tau"], oracle.MODE_SCORED)
 
-    ace = ACE(W, K, L, **ace_kwargs)
+    if signs is None:
+        ace = ACE(W, K, L, **ace_kwargs)
+    else:
+        ace = ACE(None, K, L, signs=signs, d=X.shape[1], **ace_kwargs)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).to(device)
     codes_g = codes_as_uint16(ace.hash(Xd))
     bad, n_amb, n_diff = compare_codes(codes_g, codes_o, amb)

@@ -113,3 +113,20 @@ def test_exact_score_rejects_bad_arguments():
     assert lib.ace_exact_score(None, 0, None, 0, 4, 65, None, None, 0, None) == 1             # K > 64
     assert lib.ace_exact_score(None, 0, None, 0, 0, 3, None, None, 0, None) == 1              # d = 0
     assert lib.ace_exact_score(None, -1, None, 0, 4, 3, None, None, 0, None) == 1             # m < 0
+
+
+def test_create_structured_rejects_bad_arguments():
+    from paper_1706_06664_amd.ace import Config
+    lib = _lib()
+    h = ctypes.c_void_p()
+    signs = np.zeros((1, 3, 64), np.uint8)
+    cfg = Config(8, 6, 4, 1, 1, 0, 0, 0, 0, 0)          # BF16: structured projections are FP32 only
+    assert lib.ace_create_structured(ctypes.byref(cfg), signs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == 1
+    cfg = Config(5000, 6, 4, 0, 1, 0, 0, 0, 0, 0)       # dp would exceed 4096
+    assert lib.ace_create_structured(ctypes.byref(cfg), signs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == 1
+    cfg = Config(8, 6, 4, 0, 1, 0, 0, 0, 0, 0)
+    bad = signs.copy()
+    bad[0, 1, 3] = 2                                    # a sign byte other than 0 / 1
+    assert lib.ace_create_structured(ctypes.byref(cfg), bad.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == 1
+    assert lib.ace_create_structured(ctypes.byref(cfg), None, ctypes.byref(h)) == 1
+    assert h.value is None
