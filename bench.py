@@ -219,7 +219,7 @@ def heavy_tail_runs(steps):
     return out
 
 
-def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536):
+def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=False):
     """Serving workload: d = 256, K = 15, L = 50.  A request log of n_req requests (70%
     inserts, 30% scores; lognormal sizes, median 256 rows, sigma 1, at most 65,536 rows)
     replayed against a 262,144-row pinned pool of drifting-mixture rows through the serving
@@ -242,7 +242,8 @@ def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536)
 
     def run(prec, arr=None):
         ace = ACE(W, K, L, precision=prec)
-        srv = ace.server(slots=slots, max_rows=65_536, gather_max_bytes=gather_max_bytes, batch_rows=batch_rows)
+        srv = ace.server(slots=slots, max_rows=65_536, gather_max_bytes=gather_max_bytes, batch_rows=batch_rows,
+                         graphs=graphs)
         srv.replay(rec[:500], poolp, s_out, T_out, pinned=True)   # warm-up
         srv.reset_stats()
         r = rec.copy()
@@ -256,12 +257,12 @@ def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536)
         return {"points_per_s": st["rows"] / wall, "requests_per_s": st["requests"] / wall,
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "p99_queue_ms": st["p99_queue_ms"],
                 "max_ms": st["max_ms"], "batches": st["batches"],
-                "mean_batch_requests": st["mean_batch_requests"]}
+                "mean_batch_requests": st["mean_batch_requests"], "graph_launches": st["graph_launches"]}
 
     out = {"workload": f"serving d={d}, K={K}, L={L}: {n_req} requests, {int(n.sum())} rows, 70% inserts, "
                        f"lognormal sizes (median 256, sigma 1)",
            "server": {"slots": slots, "batch_rows": batch_rows, "gather_max_bytes": gather_max_bytes,
-                      "max_rows": 65_536}}
+                      "max_rows": 65_536, "graphs": graphs}}
     for prec in ("fp32", "bf16"):
         log(f"serving closed loop {prec}")
         out[f"closed_loop_{prec}"] = run(prec)
@@ -406,6 +407,8 @@ def main():
         torch.cuda.empty_cache()
         extra["heavy_tail_4096"] = heavy_tail_runs(max(2, args.steps // 8))
         extra["serving_256"] = serving_runs()
+        log("serving with captured graphs")
+        extra["serving_256_graphs"] = serving_runs(graphs=True)
         log("exact S(q, D) and estimator study")
         extra["exact_score_connection_log"] = exact_score_runs(X, W, K)
         log(f"  {extra['exact_score_connection_log']['ms_per_launch']:.3f} ms per launch")

@@ -310,6 +310,10 @@ typedef struct {
     int64_t max_rows;           /* rows per request and per batch, 1..2^24 */
     int64_t gather_max_bytes;   /* pinned requests of at most this many bytes of rows go to the
                                    gather kernel, larger ones to a copy; 0 = 64 KiB, -1 = never */
+    int32_t use_graphs;         /* 1: the hash part of each batch is one hipGraph launch (captured
+                                   once per slot and row bucket: multiples of 256 rows up to 8192,
+                                   then powers of two); 0: separate launches */
+    int32_t reserved;           /* must be 0 */
 } ace_server_config;
 
 typedef struct {
@@ -331,6 +335,7 @@ typedef struct {
     double mean_batch_requests;          /* requests per batch */
     int64_t gathered_requests;           /* requests whose rows the gather kernel read */
     double p50_queue_ms, p99_queue_ms;   /* arrival to the launch of the request's batch */
+    int64_t graph_launches, graph_captures;
 } ace_server_stats;
 
 /* Create a server owning ctx's request stream.  ACE_E_INVALID on a bad config,

@@ -79,7 +79,7 @@ class Counters(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("max_rows", ctypes.c_int64),
-                ("gather_max_bytes", ctypes.c_int64)]
+                ("gather_max_bytes", ctypes.c_int64), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -89,7 +89,8 @@ class ServerStats(ctypes.Structure):
                 ("p99_insert_ms", ctypes.c_double), ("p99_score_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
                 ("batches", ctypes.c_int64), ("mean_batch_requests", ctypes.c_double),
                 ("gathered_requests", ctypes.c_int64), ("p50_queue_ms", ctypes.c_double),
-                ("p99_queue_ms", ctypes.c_double)]
+                ("p99_queue_ms", ctypes.c_double), ("graph_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64)]
 
 
 _lib = None
@@ -211,9 +212,9 @@ class ACE:
             self.h = None
 
     def server(self, slots: int = 4, max_rows: int = 65536, gather_max_bytes: int = 0,
-               batch_rows: int = 0) -> "Server":
+               batch_rows: int = 0, graphs: bool = False) -> "Server":
         """Attach a serving loop (request queue, `slots` batches in flight)."""
-        return Server(self, slots, max_rows, gather_max_bytes, batch_rows)
+        return Server(self, slots, max_rows, gather_max_bytes, batch_rows, graphs)
 
     def __del__(self):
         try:
@@ -359,11 +360,11 @@ class Server:
     streams; a score sees exactly the inserts admitted before it."""
 
     def __init__(self, ace: ACE, slots: int = 4, max_rows: int = 65536, gather_max_bytes: int = 0,
-                 batch_rows: int = 0):
+                 batch_rows: int = 0, graphs: bool = False):
         if getattr(ace, "_server", None) is not None:
             raise AceError(6, "ace_server_create")
         self.ace, self.lib, self.d = ace, ace.lib, ace.d
-        cfg = ServerConfig(int(slots), int(batch_rows), int(max_rows), int(gather_max_bytes))
+        cfg = ServerConfig(int(slots), int(batch_rows), int(max_rows), int(gather_max_bytes), 1 if graphs else 0, 0)
         h = ctypes.c_void_p()
         _check(self.lib.ace_server_create(ace.h, ctypes.byref(cfg), ctypes.byref(h)), "ace_server_create")
         self.h = h

@@ -204,7 +204,8 @@ int pick_tw(int L, bool fp32) {
 
 // Hash rows [0, n) of X (one chunk of at most w->rows rows) into the workspace codes
 // [L][n]: projection + sign-pack, then the FP64 pass over the queued projections.
-ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s) {
+ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s,
+                           const int64_t* n_dev, bool count_bits) {
     ace_status st = check(c, launch_zero(w->list_count, sizeof(u64), s));
     if (st) return st;
     if (want_refined) {
@@ -238,8 +239,9 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
     a.wbC = c->wbA ? c->wbA + 2 * c->NP : nullptr;
     a.wbE = c->wbA ? c->wbA + 3 * c->NP : nullptr;
     a.norm_up = (float)(1.0 + ldexp((double)c->DP + 2.0, -23));
+    a.n_dev = n_dev;
     const bool vec = (c->cfg.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15u) == 0);
-    c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
+    if (count_bits) c->bits_hashed += (u64)n * (u64)c->cfg.K * (u64)c->cfg.L;
     if (c->cfg.precision == ACE_FP8E4M3) {
         {
             Bracket br(c, s, CLS_CONVERT, n);

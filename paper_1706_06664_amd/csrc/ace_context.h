@@ -79,7 +79,10 @@ ace_status ws_alloc(ace_ctx c, Workspace* w, int64_t rows);
 void ws_free(Workspace* w);
 ace_status check(ace_ctx c, hipError_t e);
 // Hash rows [0, n) of X into w->codes [L][n] (projection + sign-pack, then the FP64
-// pass over the queued projections when refine = 1).
-ace_status hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s);
+// pass over the queued projections when refine = 1).  n_dev (may be null): device count of
+// the real rows (<= n); rows beyond it get no codes and no refinement, so a graph captured
+// for n rows serves any smaller batch.  count_bits: add n K L to the hashed-bit counter.
+ace_status hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s,
+                      const int64_t* n_dev = nullptr, bool count_bits = true);
 
 }  // namespace ace

@@ -61,6 +61,9 @@ struct HashArgs {
     int32_t dp;            // transform size, a power of two in 64 .. 4096
     int32_t nblk;          // blocks of dp outputs
     int32_t rows_per_wave;
+    // Rows that are real (the rest of the n rows are masked out: no codes, no refinement);
+    // null means all n.  Lets one captured graph serve every batch of up to n rows.
+    const int64_t* n_dev;
 };
 
 // Arguments of the FP64 pass over the queued projections.

@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     // MFMAs run.
     const int lr = tid >> 1, lk = (tid & 1) * 16;
     const int64_t grow_ld = row0 + lr;
+    const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows (loads stay within the n rows)
     const bool row_ok = grow_ld < a.n;
     const uint16_t* xh = a.Xh + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
     const uint16_t* xl = a.Xl + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     uint32_t rok = 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-        rok |= (row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3) < a.n) ? (1u << e) : 0u;
+        rok |= (row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
     // Row norms of this lane's 16 rows (four consecutive rows per row block); rows past
     // n read row n-1's values, which only matter for rows that store nothing.
     float rA[4][4], rB[4][4], rC[4][4];
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
                                             __ballot(p[b][2] > 0.f), __ballot(p[b][3] > 0.f), lane);
             code = (kin == b) ? cb : code;
         }
-        if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+        if (table < a.L && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
     if (__any(n_ref != 0 || n_unc != 0)) {
         const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);

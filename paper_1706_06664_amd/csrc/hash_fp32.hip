@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t row0 = tile_m * BM;
+    const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows (loads stay within the n rows)
     const int col0 = (int)tile_n * NB;
 
     f4 acc[4][TW];
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             rbnd[4 * b + r] = v[r];
-            rok |= (row0 + wm * 64 + 16 * b + 4 * kin + r < a.n) ? (1u << (4 * b + r)) : 0u;
+            rok |= (row0 + wm * 64 + 16 * b + 4 * kin + r < nv) ? (1u << (4 * b + r)) : 0u;
         }
     }
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
                                             __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
             code = (kin == b) ? cb : code;
         }
-        if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+        if (table < a.L && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
     if (__any(n_ref != 0 || n_unc != 0)) {
         const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);

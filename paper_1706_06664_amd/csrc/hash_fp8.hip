@@ -165,6 +165,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     // spread over the block otherwise.
     const int lr = tid >> 1, lk = (tid & 1) * 64;
     const int64_t grow_ld = row0 + lr;
+    const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows (loads stay within the n rows)
     const bool row_ok = grow_ld < a.n;
     const uint8_t* xq = a.Xq + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
     constexpr int WQ = NB * (BKB / 16);          // 16-byte quads in the W tile
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         int64_t g = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
-        rok |= (g < a.n) ? (1u << e) : 0u;
+        rok |= (g < nv) ? (1u << e) : 0u;
         g = g < a.n ? g : a.n - 1;
         rA[e] = a.rowA[g];
         rB[e] = a.rowB[g];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
                                             __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
             code = (kin == b) ? cb : code;
         }
-        if (table < a.L && orow < a.n) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+        if (table < a.L && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
     if (__any(n_ref != 0 || n_unc != 0)) {
         const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);

@@ -145,10 +145,11 @@ __global__ __launch_bounds__(256) void hash_struct_kernel(const HashArgs a) {
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t rows_per_block = 4 * (int64_t)a.rows_per_wave;
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
+    const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows
 
     for (int rw = 0; rw < a.rows_per_wave; ++rw) {
         const int64_t row = (int64_t)blockIdx.x * rows_per_block + (int64_t)wave * a.rows_per_wave + rw;
-        if (row >= a.n) break;   // uniform over the wave
+        if (row >= nv) break;   // uniform over the wave
         const float* xr = a.X + row * (int64_t)a.d;
         float E = 0.f;
         for (int b = 0; b < a.nblk; ++b) {

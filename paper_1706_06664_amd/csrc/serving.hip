@@ -9,7 +9,11 @@
 // phase: one count-update or score launch per run of consecutive same-kind requests, in
 // admission order -> device-to-host copy of s and T.  A completion thread polls the
 // events of busy slots, copies each request's outputs to the caller, records its latency
-// and frees the slot.
+// and frees the slot.  With use_graphs, the hash part of a batch is one hipGraph launch:
+// the pipeline (list reset, conversion, projection, FP64 pass) is captured once per slot and
+// row bucket (multiples of 256 rows up to 8192, then powers of two), and the kernels read the
+// batch's real row count from
+// a device word that a small copy sets before each launch.
 //
 // Ordering.  Hashing reads only the rows and W, so hashes of different batches overlap
 // freely.  The count phase of a batch waits (hipStreamWaitEvent) on the count phase of the
@@ -102,6 +106,9 @@ struct Slot {
     GatherTask* tasks_h = nullptr;   // pinned: gather tasks of the batch
     GatherTask* tasks_d = nullptr;   // device copy read by the gather kernel
     int64_t task_cap = 0;
+    int64_t* n_dev = nullptr;        // real rows of the batch (read by the captured hash)
+    int64_t* n_host = nullptr;       // pinned source of n_dev
+    std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;   // hash pipeline per row bucket
     int state = SLOT_FREE;
     bool has_score = false;
     std::vector<Req> reqs;     // the batch in flight
@@ -134,7 +141,7 @@ struct ace_server_s {
     std::vector<uint8_t> done_of;
     std::vector<uint8_t> kind_of;
     std::vector<int64_t> rows_of;
-    int64_t batches = 0, batched_requests = 0, gathered_requests = 0;
+    int64_t batches = 0, batched_requests = 0, gathered_requests = 0, graph_launches = 0, graph_captures = 0;
     int next_slot = 0;
     int last_slot = -1;              // slot of the most recently dispatched batch
     bool have_first = false;
@@ -209,6 +216,28 @@ void completion_loop(ace_server srv) {
     }
 }
 
+// Capture the hash pipeline of a B-row bucket on the slot's stream (thread-local capture:
+// the completion thread's event queries go on) and instantiate it.  The list reset inside
+// is a fill kernel, not a memset.
+ace_status capture_hash(ace_server srv, Slot& sl, int64_t B, hipGraphExec_t* out) {
+    ace_ctx c = srv->c;
+    const int prof = c->profiling;
+    c->profiling = 0;   // no event records inside the graph
+    ace_status st = check(c, hipStreamBeginCapture(sl.s, hipStreamCaptureModeThreadLocal));
+    if (st) {
+        c->profiling = prof;
+        return st;
+    }
+    const ace_status hs = hash_chunk(c, &sl.ws, sl.Xd, B, false, sl.s, sl.n_dev, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(sl.s, &g);
+    c->profiling = prof;
+    st = hs ? hs : check(c, e);
+    if (!st) st = check(c, hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
 // Enqueue one batch on its slot's stream (dispatcher thread, no lock held).
 ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait_cnt) {
     ace_ctx c = srv->c;
@@ -256,7 +285,40 @@ ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait
         }
     }
     // Hashing does not read the counts: it overlaps with the batches in flight.
-    st = st ? st : hash_chunk(c, &sl.ws, sl.Xd, rows, false, sl.s);
+    int64_t ldc = rows;
+    if (srv->cfg.use_graphs) {
+        // One graph launch: the hash pipeline captured once per slot for a bucket of B rows
+        // (multiples of 256 up to 8192, then powers of two; at most max_rows), so at most 255
+        // padded rows per small batch; the batch's row count goes to n_dev.
+        int64_t B = (rows + 255) / 256 * 256;
+        if (B > 8192) {
+            B = 16384;
+            while (B < rows) B *= 2;
+        }
+        if (B > srv->cfg.max_rows) B = srv->cfg.max_rows;
+        hipGraphExec_t ex = nullptr;
+        for (auto& g : sl.graphs)
+            if (g.first == B) ex = g.second;
+        if (!st && !ex) {
+            st = capture_hash(srv, sl, B, &ex);
+            if (!st) {
+                sl.graphs.push_back({B, ex});
+                ++srv->graph_captures;
+            }
+        }
+        if (!st) {
+            *sl.n_host = rows;
+            st = check(c, hipMemcpyAsync(sl.n_dev, sl.n_host, sizeof(int64_t), hipMemcpyHostToDevice, sl.s));
+        }
+        if (!st) {
+            st = check(c, hipGraphLaunch(ex, sl.s));
+            c->bits_hashed += (u64)rows * (u64)c->cfg.K * (u64)c->cfg.L;
+            ++srv->graph_launches;
+        }
+        ldc = B;
+    } else {
+        st = st ? st : hash_chunk(c, &sl.ws, sl.Xd, rows, false, sl.s);
+    }
     // Count phase, after the previous batch's count phase: one launch per run of
     // consecutive requests of one kind, in admission order.
     if (wait_cnt) st = st ? st : check(c, hipStreamWaitEvent(sl.s, wait_cnt, 0));
@@ -266,12 +328,12 @@ ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait
         const int64_t off = sl.reqs[i].off;
         int64_t len = 0;
         for (; i < sl.reqs.size() && sl.reqs[i].kind == kind; ++i) len += sl.reqs[i].n;
-        const uint16_t* codes = sl.ws.codes + off;   // table j of row r at codes[j * rows + r]
+        const uint16_t* codes = sl.ws.codes + off;   // table j of row r at codes[j * ldc + r]
         if (kind == ACE_REQ_INSERT)
-            st = check(c, launch_count_update(codes, rows, len, c->cfg.K, c->cfg.L, +1, c->counts, c->cbits, c->S2,
+            st = check(c, launch_count_update(codes, ldc, len, c->cfg.K, c->cfg.L, +1, c->counts, c->cbits, c->S2,
                                               c->S3, c->err, c->rcnt + 3, sl.s));
         else
-            st = check(c, launch_score(codes, rows, len, c->cfg.K, c->cfg.L, c->counts, c->cbits, sl.sd + off,
+            st = check(c, launch_score(codes, ldc, len, c->cfg.K, c->cfg.L, c->counts, c->cbits, sl.sd + off,
                                        sl.Td + off,
                                        c->mom, sl.s));
     }
@@ -349,11 +411,13 @@ void dispatch_loop(ace_server srv) {
 }
 
 void free_slot(Slot& sl) {
+    for (auto& g : sl.graphs) (void)hipGraphExecDestroy(g.second);
+    sl.graphs.clear();
     ws_free(&sl.ws);
-    void* dev[] = {sl.Xd, sl.sd, sl.Td, sl.tasks_d};
+    void* dev[] = {sl.Xd, sl.sd, sl.Td, sl.tasks_d, sl.n_dev};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {sl.Xh, sl.sh, sl.Th, sl.tasks_h};
+    void* host[] = {sl.Xh, sl.sh, sl.Th, sl.tasks_h, sl.n_host};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (sl.done) (void)hipEventDestroy(sl.done);
@@ -375,12 +439,14 @@ ace_status alloc_slot(ace_ctx c, Slot& sl, int64_t rows) {
     // rows / kGatherRows + (number of requests) <= rows / kGatherRows + rows tasks.
     sl.task_cap = rows / kGatherRows + rows + 1;
     st = st ? st : dev_alloc(c, (void**)&sl.tasks_d, sizeof(GatherTask) * (size_t)sl.task_cap);
+    st = st ? st : dev_alloc(c, (void**)&sl.n_dev, sizeof(int64_t));
     if (st) return st;
     if (hipHostMalloc((void**)&sl.Xh, sizeof(float) * d * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&sl.sh, sizeof(float) * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&sl.Th, sizeof(uint32_t) * (size_t)rows, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&sl.tasks_h, sizeof(GatherTask) * (size_t)sl.task_cap, hipHostMallocDefault) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc((void**)&sl.n_host, sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return ACE_E_NOMEM;
     }
@@ -490,6 +556,7 @@ ace_status ace_server_create(ace_ctx c, const ace_server_config* cfg, ace_server
     if (c->sticky != ACE_OK) return c->sticky;
     if (cfg->slots < 1 || cfg->slots > 64 || cfg->max_rows < 1 || cfg->max_rows > ((int64_t)1 << 24)) return ACE_E_INVALID;
     if (cfg->batch_rows < 0 || cfg->gather_max_bytes < -1) return ACE_E_INVALID;
+    if ((cfg->use_graphs != 0 && cfg->use_graphs != 1) || cfg->reserved != 0) return ACE_E_INVALID;
     if (c->server_attached) return ACE_E_STATE;
     DevGuard g(c->cfg.device);
     ace_server srv = new ace_server_s();
@@ -615,6 +682,8 @@ ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     s.batches = srv->batches;
     s.mean_batch_requests = srv->batches ? (double)srv->batched_requests / (double)srv->batches : 0.0;
     s.gathered_requests = srv->gathered_requests;
+    s.graph_launches = srv->graph_launches;
+    s.graph_captures = srv->graph_captures;
     s.p50_queue_ms = percentile(qw, 50.0);
     s.p99_queue_ms = percentile(qw, 99.0);
     *out = s;
@@ -632,7 +701,7 @@ ace_status ace_server_reset_stats(ace_server srv) {
     srv->done_of.clear();
     srv->kind_of.clear();
     srv->rows_of.clear();
-    srv->batches = srv->batched_requests = srv->gathered_requests = 0;
+    srv->batches = srv->batched_requests = srv->gathered_requests = srv->graph_launches = 0;
     srv->have_first = false;
     return ACE_OK;
 }

@@ -80,7 +80,7 @@ def test_server_calls_reject_null_handles():
     lib = _lib()
     from paper_1706_06664_amd.ace import ServerConfig, ServerStats
     h = ctypes.c_void_p()
-    cfg = ServerConfig(2, 0, 16, 0)
+    cfg = ServerConfig(2, 0, 16, 0, 0, 0)
     assert lib.ace_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == 1
     assert h.value is None
     X = np.zeros((4, 8), np.float32)
@@ -101,8 +101,8 @@ def test_request_record_layout_matches_header():
     assert REQUEST_DTYPE.itemsize == 40
     assert [REQUEST_DTYPE.fields[f][1] for f in ("kind", "pad", "n", "row0", "out0", "t_arrival_s")] == \
         [0, 4, 8, 16, 24, 32]
-    assert ctypes.sizeof(ServerConfig) == 24
-    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16
+    assert ctypes.sizeof(ServerConfig) == 32
+    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16 + 16
 
 
 def test_exact_score_rejects_bad_arguments():

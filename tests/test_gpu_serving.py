@@ -46,15 +46,19 @@ def _oracle_replay(kind, n, row0, out0, pool, W, K, L):
     return T, sk, int(np.count_nonzero(amb))
 
 
-@pytest.mark.parametrize("precision,d,slots,nreq,pinned,gmb,br", [
-    ("fp32", 64, 1, 300, False, 0, 0), ("fp32", 64, 8, 300, False, 0, 0), ("fp32", 61, 3, 300, True, 1 << 30, 0),
-    ("fp32", 64, 4, 300, True, 0, 100), ("bf16", 256, 4, 200, True, 0, 0), ("bf16", 256, 2, 200, False, 0, 0),
-    ("fp8", 256, 6, 200, True, -1, 0)])
-def test_serving_equals_sequential_replay(precision, d, slots, nreq, pinned, gmb, br):
+@pytest.mark.parametrize("precision,d,slots,nreq,pinned,gmb,br,graphs", [
+    ("fp32", 64, 1, 300, False, 0, 0, False), ("fp32", 64, 8, 300, False, 0, 0, False),
+    ("fp32", 61, 3, 300, True, 1 << 30, 0, False), ("fp32", 64, 4, 300, True, 0, 100, False),
+    ("bf16", 256, 4, 200, True, 0, 0, False), ("bf16", 256, 2, 200, False, 0, 0, False),
+    ("fp8", 256, 6, 200, True, -1, 0, False),
+    ("fp32", 64, 4, 300, True, 0, 100, True), ("fp32", 61, 1, 300, False, 0, 0, True),
+    ("bf16", 256, 4, 200, True, 0, 300, True), ("fp8", 256, 3, 200, False, 0, 0, True)])
+def test_serving_equals_sequential_replay(precision, d, slots, nreq, pinned, gmb, br, graphs):
     """Closed loop (every request queued at once), so batches mix inserts and scores.  With
     pinned rows, requests of at most gmb bytes are read by the gather kernel (d=61 takes its
     unaligned path), larger ones by copies (0: the 64 KiB default, -1: never gather).
-    br: target rows per batch (0 = max_rows)."""
+    br: target rows per batch (0 = max_rows).  graphs: the hash of each batch is a replay of a
+    captured graph (one per slot and row bucket), so every replay is checked here."""
     import torch
     from paper_1706_06664_amd import ACE
     K, L = 15, 50
@@ -64,7 +68,7 @@ def test_serving_equals_sequential_replay(precision, d, slots, nreq, pinned, gmb
     assert n_amb == 0   # continuous rows: no projection inside the FP64 margin
     _say(dict(precision=precision, slots=slots, requests=nreq, rows=int(n.sum()), scored=int(T_o.size)))
     ace = ACE(W, K, L, precision=precision, refine=True)
-    srv = ace.server(slots=slots, max_rows=1024, gather_max_bytes=gmb, batch_rows=br)
+    srv = ace.server(slots=slots, max_rows=1024, gather_max_bytes=gmb, batch_rows=br, graphs=graphs)
     s_out = np.full(T_o.size, -1.0, np.float32)
     T_out = np.zeros(T_o.size, np.uint32)
     src = torch.from_numpy(pool).pin_memory() if pinned else pool
@@ -78,6 +82,10 @@ def test_serving_equals_sequential_replay(precision, d, slots, nreq, pinned, gmb
         assert 0 < st["gathered_requests"] < nreq
     if br:
         assert st["batches"] >= int(n.sum()) // 1024 and st["mean_batch_requests"] < nreq / 20
+    if graphs:
+        assert st["graph_launches"] == st["batches"] and 1 <= st["graph_captures"] <= 4 * slots
+    else:
+        assert st["graph_launches"] == 0
     assert (lat >= 0).all()
     np.testing.assert_array_equal(T_out.astype(np.int64), T_o)
     np.testing.assert_allclose(s_out, T_o / L, rtol=1e-6, atol=0)
@@ -177,7 +185,7 @@ def test_server_errors():
     # a second server on the same context is refused by the library too
     from paper_1706_06664_amd.ace import ServerConfig
     h = ctypes.c_void_p()
-    cfg = ServerConfig(1, 0, 10, 0)
+    cfg = ServerConfig(1, 0, 10, 0, 0, 0)
     assert ace.lib.ace_server_create(ace.h, ctypes.byref(cfg), ctypes.byref(h)) == 6
     srv.close()
     srv2 = ace.server(slots=1, max_rows=10)
