@@ -37,7 +37,7 @@ namespace {
 
 constexpr int BM = 128;
 constexpr int BK = 32;
-constexpr int LDSB = BK + 8;  // padded LDS row stride in bf16 elements (80 bytes)
+constexpr int LDSB = BK + 16;  // padded LDS row stride in bf16 elements (96 bytes: the 16-byte fragment reads of 16 rows hit distinct banks)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -154,11 +154,11 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     s8v xhv[2], xlv[2];
     s4v whv[TW], wlv[TW];
     auto gload = [&](int k0) {
+        // rows past n read row 0 of the chunk (their results are masked)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const s8v z = s8v{0, 0, 0, 0, 0, 0, 0, 0};
-            xhv[h] = row_ok ? *reinterpret_cast<const s8v*>(xh + k0 + 8 * h) : z;
-            xlv[h] = row_ok ? *reinterpret_cast<const s8v*>(xl + k0 + 8 * h) : z;
+            xhv[h] = *reinterpret_cast<const s8v*>(xh + k0 + 8 * h);
+            xlv[h] = *reinterpret_cast<const s8v*>(xl + k0 + 8 * h);
         }
 #pragma unroll
         for (int s = 0; s < TW; ++s) {
