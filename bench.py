@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
-KERNEL = {"fp32": "hash_fp32_kernel", "bf16": "hash_bf16_kernel"}
+KERNEL = {"fp32": "hash_fp32_direct_kernel", "bf16": "hash_bf16_kernel"}
 
 
 def log(msg):
@@ -119,7 +119,7 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     rows = prof["hash_rows"] / max(1, prof["hash_launches"])
     flop = 2.0 * rows * d * K * L
     executed = flop * (16.0 / K) * (3.0 if precision == "bf16" else 1.0)
-    kernel = {"fp32": "hash_fp32_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}[precision]
+    kernel = {"fp32": "hash_fp32_direct_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}[precision]
     if signs is not None:
         kernel = "hash_struct_kernel"
     ach = flop / (hash_ms / 1e3)
@@ -420,7 +420,7 @@ def main():
 
     roof = dict(head["roofline"])
     tb = recorded_traffic("paper_1706_06664_amd/csrc/hash_fp32.hip",
-                          "profiles/hash_fp32_kernel__connection_log_494021x120.md")
+                          "profiles/hash_fp32_direct_kernel__connection_log_494021x120.md")
     if tb is not None:
         roof["traffic"] = tb
         roof["traffic_unit"] = "bytes/launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)"

@@ -164,6 +164,71 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
     }
 }
 
+// One workgroup per table (K <= 15): the workgroup histograms every row of its table in
+// LDS, then moves each bucket once.  It is the only writer of that table during the
+// launch, so the counts are read and written plainly (no atomics); the S2/S3 deltas come
+// from the old and new value of each bucket, as in the merged kernel.  Grid: L blocks.
+template <bool C16>
+__global__ __launch_bounds__(HIST_THREADS) void update_table_kernel(const uint16_t* __restrict__ codes, int64_t ldc,
+                                                                    int64_t n, int K, int sign,
+                                                                    void* __restrict__ counts_v, u64* __restrict__ S2,
+                                                                    u64* __restrict__ S3, unsigned* __restrict__ err,
+                                                                    u64* __restrict__ drops) {
+    extern __shared__ uint32_t hist[];
+    __shared__ u64 red[3 * (HIST_THREADS / 64)];
+    const int j = blockIdx.x;
+    const int64_t B = (int64_t)1 << K;
+    for (int64_t w = threadIdx.x; w < B; w += blockDim.x) hist[w] = 0u;
+    __syncthreads();
+    const uint16_t* cj = codes + (int64_t)j * ldc;
+    const uint32_t bmask = (uint32_t)(B - 1);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&hist[cj[i] & bmask], 1u);
+    __syncthreads();
+    u64 s2 = 0, s3lo = 0, s3hi = 0, dropped = 0;
+    unsigned bad = 0;
+    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+        const uint32_t h = hist[b];
+        if (!h) continue;
+        int64_t old, nw;
+        if (C16) {
+            uint16_t* c = reinterpret_cast<uint16_t*>(counts_v) + (int64_t)j * B + b;
+            old = *c;
+            nw = sign > 0 ? old + (int64_t)h : old - (int64_t)h;
+            if (nw > 65535) {
+                dropped += (u64)(nw - 65535);
+                nw = 65535;
+            }
+            if (nw < 0) {
+                bad = 1;
+                nw = 0;
+            }
+            *c = (uint16_t)nw;
+        } else {
+            int32_t* c = reinterpret_cast<int32_t*>(counts_v) + (int64_t)j * B + b;
+            old = *c;
+            nw = sign > 0 ? old + (int64_t)h : old - (int64_t)h;
+            if (nw < 0) bad = 1;
+            *c = (int32_t)nw;
+        }
+        u64 d2, d3lo, d3hi;
+        sq_cube_delta(old, nw - old, d2, d3lo, d3hi);
+        s2 += d2;
+        add128(s3lo, s3hi, d3lo, d3hi);
+    }
+    if (__any(bad)) {
+        if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
+    }
+    if (C16) {
+        dropped = wave_sum_u64(dropped);
+        if ((threadIdx.x & 63) == 0 && dropped) atomicAdd(drops, dropped);
+    }
+    block_sum3(s2, s3lo, s3hi, red);
+    if (threadIdx.x == 0) {
+        if (s2) atomicAdd(&S2[j], s2);
+        atomic_add_u128(&S3[2 * j], s3lo, s3hi);
+    }
+}
+
 // Direct update for small batches: one thread per (row, table), one global atomic each.
 // Grid: (ceil(n/256), L).
 template <bool C16>
@@ -329,7 +394,9 @@ __global__ __launch_bounds__(256) void zero_kernel(uint32_t* __restrict__ p, int
 }  // namespace
 
 hipError_t init_kernel_attributes() {
-    const void* fns[] = {reinterpret_cast<const void*>(&update_lds_kernel<false, false>),
+    const void* fns[] = {reinterpret_cast<const void*>(&update_table_kernel<false>),
+                         reinterpret_cast<const void*>(&update_table_kernel<true>),
+                         reinterpret_cast<const void*>(&update_lds_kernel<false, false>),
                          reinterpret_cast<const void*>(&update_lds_kernel<true, false>),
                          reinterpret_cast<const void*>(&update_lds_kernel<false, true>),
                          reinterpret_cast<const void*>(&update_lds_kernel<true, true>)};
@@ -356,6 +423,18 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
         else
             hipLaunchKernelGGL(update_direct_kernel<false>, dim3((unsigned)nb, (unsigned)L), dim3(256), 0, s, codes,
                                ldc, n, K, sign, counts, S2, S3, err, drops);
+        return hipGetLastError();
+    }
+    // 16-bit counters, enough tables to fill a good part of the chip and a table that fits
+    // in LDS: one workgroup per table (plain stores instead of compare-and-swap loops).
+    if (c16 && K <= 15 && L >= 32) {
+        const size_t lds = (size_t)B * sizeof(uint32_t);
+        if (c16)
+            hipLaunchKernelGGL(update_table_kernel<true>, dim3((unsigned)L), dim3(HIST_THREADS), lds, s, codes, ldc,
+                               n, K, sign, counts, S2, S3, err, drops);
+        else
+            hipLaunchKernelGGL(update_table_kernel<false>, dim3((unsigned)L), dim3(HIST_THREADS), lds, s, codes, ldc,
+                               n, K, sign, counts, S2, S3, err, drops);
         return hipGetLastError();
     }
     int64_t chunks = (n + B / 2 - 1) / (B / 2);

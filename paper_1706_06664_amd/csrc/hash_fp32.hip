@@ -19,10 +19,12 @@
 // of FP32 values are exact in FP64, so this is the same value a plain FP64 loop
 // produces).
 //
-// Tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns).  A workgroup tile is
-// 128 rows x 2*TW tables (32*TW padded columns); each wave holds 64 rows x TW
-// tables = 4 x TW MFMA tiles of 16x16.  The contraction runs in chunks of 32 through
-// LDS; both operands are stored k-contiguous so each lane reads one float4 per
+// Two kernels.  Rows that are 16-byte aligned with d % 4 == 0 go to the direct kernel
+// (operands loaded straight into registers, persistent grid); other inputs go to the LDS
+// kernel.  LDS kernel tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns).  A
+// workgroup tile is 128 rows x 2*TW tables (32*TW padded columns); each wave holds 64
+// rows x TW tables = 4 x TW MFMA tiles of 16x16.  The contraction runs in chunks of 32
+// through LDS; both operands are stored k-contiguous so each lane reads one float4 per
 // 16-wide k block and feeds four MFMAs with it.
 #include "ace_internal.h"
 
@@ -33,6 +35,9 @@ namespace {
 constexpr int BM = 128;
 constexpr int BK = 32;
 constexpr int LDSW = BK + 4;  // padded LDS row stride (floats)
+// Direct kernel: 16-row blocks per wave and resident waves per SIMD (its register budget).
+constexpr int DIRECT_RB = 4;
+constexpr int DIRECT_WAVES = 2;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -47,6 +52,97 @@ __device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane)
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Epilogue shared by the projection kernels.  acc[b][t] (b < RB) is the 16x16 MFMA tile of
+// rows rbase + 16b .. and padded columns cbase + 16t ..; lane l holds rows 16b + 4(l/16) + r
+// (r = 0..3) of column l%16.  rbnd[4b + r] is the row bound factor of that row and wcol[t]
+// the column factor of this lane's column in tile t.  Projections inside their bound are
+// queued for the FP64 pass (or decided here when the queue is full); each 16-column tile
+// is one table, whose bits are gathered with ballots and stored as one uint16 per row.
+template <int TW, int RB>
+__device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const float (&rbnd)[4 * RB],
+                                     const float (&wcol)[TW], int64_t rbase, int cbase, int64_t nv, int lane) {
+    const int kin = lane >> 4, cl = lane & 15;
+    uint32_t rok = 0;
+#pragma unroll
+    for (int e = 0; e < 4 * RB; ++e) rok |= (rbase + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+    const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
+    const int64_t orow = rbase + lane;  // the row whose codes this lane stores (lanes < 16 RB)
+    uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const int table = (cbase >> 4) + t;
+        const int cp = cbase + t * 16 + cl;
+        const float wbv = wcol[t];
+        // Bit e of pos: sign of accumulator element e; bit e of umask: inside the bound.
+        uint32_t umask = 0, pos = 0;
+        const bool chk = a.refine && wbv >= 0.f;
+#pragma unroll
+        for (int e = 0; e < 4 * RB; ++e) {
+            const float p = acc[e >> 2][t][e & 3];
+            pos |= (p > 0.f) ? (1u << e) : 0u;
+            const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
+            umask |= (chk && !(fabsf(p) > thr)) ? (1u << e) : 0u;  // NaN is uncertain too
+        }
+        umask &= rok;
+        if (a.refine == 2) {
+            n_unc += __popc(umask);  // count only: the raw signs stand
+            umask = 0;
+        }
+        if (__any(umask != 0)) {
+            // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave.
+            const uint32_t mine = __popc(umask);
+            uint32_t incl = mine;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            u64 base = 0;
+            if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
+            base = __shfl(base, 0, 64);
+            u64 slot = base + (incl - mine);
+            uint32_t todo = umask;
+            while (todo) {
+                const int e = __builtin_ctz(todo);
+                todo &= todo - 1u;
+                const int64_t grow = rbase + 16 * (e >> 2) + 4 * kin + (e & 3);
+                const bool raw = (pos >> e) & 1u;
+                if (slot < a.list_cap) {
+                    a.list[slot] = (u64)(uint32_t)grow | ((u64)cp << 32) | (raw ? (1ull << 63) : 0ull);
+                } else {
+                    // Queue full: decide here (same FP64 sum as the FP64 pass).
+                    const float* xr = a.X + grow * (int64_t)a.d;
+                    const float* wr = a.Wt + (int64_t)cp * a.DP;
+                    double sacc = 0.0;
+                    for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
+                    n_ref += 1u;
+                    n_flip += ((sacc > 0.0) != raw) ? 1u : 0u;
+                    pos = sacc > 0.0 ? (pos | (1u << e)) : (pos & ~(1u << e));
+                }
+                ++slot;
+            }
+        }
+        uint32_t code = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const uint32_t cb = select_code(__ballot((pos >> (4 * b)) & 1u), __ballot((pos >> (4 * b + 1)) & 1u),
+                                            __ballot((pos >> (4 * b + 2)) & 1u), __ballot((pos >> (4 * b + 3)) & 1u),
+                                            lane);
+            code = (kin == b) ? cb : code;
+        }
+        if (table < a.L && lane < 16 * RB && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
+    }
+    if (__any(n_ref != 0 || n_unc != 0)) {
+        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);
+        if (lane == 0) {
+            if (r) atomicAdd(&a.counters[0], (u64)r);
+            if (f) atomicAdd(&a.counters[1], (u64)f);
+            if (uc) atomicAdd(&a.counters[2], (u64)uc);
+        }
+    }
 }
 
 template <int TW, bool VEC>
@@ -154,88 +250,226 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
     __syncthreads();
 
     // This lane's 16 accumulator rows: wm*64 + 16b + 4*kin + r (b, r = 0..3), index e = 4b + r.
-    const int kin = lane >> 4, cl = lane & 15;
+    const int kin = lane >> 4;
     float rbnd[16];
-    uint32_t rok = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const f4 v = *reinterpret_cast<const f4*>(rowb + wm * 64 + 16 * b + 4 * kin);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            rbnd[4 * b + r] = v[r];
-            rok |= (row0 + wm * 64 + 16 * b + 4 * kin + r < nv) ? (1u << (4 * b + r)) : 0u;
-        }
+        for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = v[r];
     }
-    const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
-    const int64_t orow = row0 + wm * 64 + lane;  // the row whose codes this lane stores
-    uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
+    sign_epilogue<TW, 4>(a, acc, rbnd, wcol, row0 + wm * 64, col0 + wn * TW * 16, nv, lane);
+}
+
+// Direct-operand variant (d % 4 == 0, 16-byte aligned rows): each wave loads its MFMA
+// operands from global memory straight into registers, one 16-byte load per lane for each
+// 16-row (or 16-column) tile and 16-wide k block, issued one block ahead of the MFMAs that
+// use them.  No LDS and no barriers: the four waves of a workgroup run on their own, and
+// the two waves that share rows (or columns) share them through the CU's L1 and the XCD's
+// L2.  Lane l feeds k = kb + 4(l/16) + s to MFMA step s, for rows (A) and columns (B)
+// alike.  The last partial block of d takes only the steps it needs: 2 for 8 remaining
+// k (k = kb + 2(l/16) + s), 1 for 4 (k = kb + l/16); with 12 the fourth k group is zero.
+// Rows past n read as zero (range-checked buffer loads over the wave's rows).
+//
+// The grid is persistent: workgroup g takes tile slots g, g + G, g + 2G, ... (G, the grid
+// size, is a multiple of 8, so every slot of a workgroup maps to the same XCD), and the
+// rows of the first k block of a wave's next tile are loaded before the sign epilogue of
+// its current one, so that load's latency is spent on the epilogue.
+//
+// Tiling: 4 waves as 2 (rows) x 2 (columns); a wave holds RB 16-row blocks x TW tables.
+//
+// Row norm: each lane sums the squares of its k values in FP32 (one rounding per fused
+// multiply-add, at most d/4 + 3 of them); the four k groups are added in FP64.  The sum is
+// scaled by norm_up = 1 + (DP + 2) 2^-23 >= 1 + gamma_{d/4+3}(2^-24), and (d + 16) 2^-125
+// is added for squares lost below the normal range: an upper bound of ||x||^2.
+template <int TW, int RB, int REM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVES, DIRECT_WAVES))) void hash_fp32_direct_kernel(
+    const HashArgs a, int64_t tiles_m, int64_t n_slots) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: buffer views in SGPRs
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t nv = a.n_dev ? *a.n_dev : a.n;
+    const int cl = lane & 15, kin = lane >> 4;
+    const int d = a.d;
+    const uint32_t xo = (uint32_t)(cl * d) * 4u, wo = (uint32_t)(cl * a.DP) * 4u;
+    const int xstep = 16 * d * 4, wstep = 16 * a.DP * 4;  // bytes per 16-row / 16-column tile
+    const int nfull = d >> 4;  // full 16-wide k blocks; REM = d - 16 nfull (0, 4, 8 or 12)
+
+    // Tile slot -> this wave's first row and first padded column; false if it has no rows.
+    auto slot_tile = [&](int64_t v, int64_t& rbase, int& cbase) -> bool {
+        const int64_t xcd = v & 7, local = v >> 3;
+        const int64_t tile_n = local % a.n_tiles_n;
+        const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
+        rbase = tile_m * (32 * RB) + wm * (16 * RB);
+        cbase = (int)tile_n * 32 * TW + wn * TW * 16;
+        return tile_m < tiles_m && rbase < a.n;
+    };
+    // Range-checked buffer views: the wave's rows of X (rows past n read as zero) and its
+    // 16 TW padded columns of W^T.  A lane's offset names its row (column) and k group;
+    // the tile index goes into the wave-uniform scalar offset.
+    auto x_view = [&](int64_t rbase) {
+        const int64_t rows_here = min((int64_t)(16 * RB), a.n - rbase);
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(a.X + rbase * (int64_t)d), (short)0,
+                                                 (int)(rows_here * d * 4), 0x00020000);
+    };
+    auto w_view = [&](int cbase) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(a.Wt + (int64_t)cbase * a.DP), (short)0,
+                                                 16 * TW * a.DP * 4, 0x00020000);
+    };
+
+    int64_t v = blockIdx.x, rbase = 0;
+    int cbase = 0;
+    while (v < n_slots && !slot_tile(v, rbase, cbase)) v += gridDim.x;
+    if (v >= n_slots) return;
+    __amdgpu_buffer_rsrc_t xs = x_view(rbase), ws = w_view(cbase);
+
+    f4 acc[RB][TW];
+    float ss[RB];
+    auto load_a = [&](int kb, f4 (&av)[RB]) {
+        const uint32_t kof = (uint32_t)(kb + 4 * kin) * 4u;
 #pragma unroll
-    for (int t = 0; t < TW; ++t) {
-        const int table = (col0 >> 4) + wn * TW + t;
-        const int cp = col0 + (wn * TW + t) * 16 + cl;
-        const float wbv = wcol[t];
-        uint32_t umask = 0;
-        if (a.refine && wbv >= 0.f) {
+        for (int b = 0; b < RB; ++b)
+            av[b] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xs, xo + kof, b * xstep, 0));
+    };
+    auto load_b = [&](int kb, f4 (&bv)[TW]) {
+        const uint32_t kof = (uint32_t)(kb + 4 * kin) * 4u;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
-                umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;  // NaN is uncertain too
+        for (int t = 0; t < TW; ++t)
+            bv[t] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(ws, wo + kof, t * wstep, 0));
+    };
+    auto load = [&](int kb, f4 (&av)[RB], f4 (&bv)[TW]) {
+        load_a(kb, av);
+        load_b(kb, bv);
+    };
+    auto step = [&](const f4 (&av)[RB], const f4 (&bv)[TW]) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ss[b] = fmaf(av[b][q], av[b][q], ss[b]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b][q], bv[t][q], acc[b][t], 0, 0, 0);
+    };
+
+    f4 ac[RB], bc[TW];
+    if (nfull > 0) load_a(0, ac);
+    for (;;) {
+        if (nfull > 0) load_b(0, bc);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            ss[b] = 0.f;
+#pragma unroll
+            for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        // Block i + 1 is loaded while block i is multiplied; two blocks per trip so that the
+        // operand registers alternate without copies.  Past the last full block the loads
+        // read the partial block or the next rows and columns: in range, and unused unless
+        // REM == 12, whose partial block it is.
+        int i = 0;
+        for (; i + 2 <= nfull; i += 2) {
+            f4 an[RB], bn[TW];
+            load(16 * (i + 1), an, bn);
+            step(ac, bc);
+            // Keep each block's norm updates (which wait for its loads) out of the previous
+            // block's MFMA stream.
+            __builtin_amdgcn_sched_barrier(0);
+            load(16 * (i + 2), ac, bc);
+            step(an, bn);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (i < nfull) {
+            f4 an[RB], bn[TW];
+            load(16 * (i + 1), an, bn);
+            step(ac, bc);
+            if constexpr (REM == 12) {
+#pragma unroll
+                for (int b = 0; b < RB; ++b) ac[b] = an[b];
+#pragma unroll
+                for (int t = 0; t < TW; ++t) bc[t] = bn[t];
             }
-            umask &= rok;
         }
-        if (a.refine == 2) {
-            n_unc += __popc(umask);  // count only: the raw signs stand
-            umask = 0;
-        }
-        if (__any(umask != 0)) {
-            // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave.
-            const uint32_t mine = __popc(umask);
-            uint32_t incl = mine;
+
+        const int kb = 16 * nfull;
+        if constexpr (REM == 12) {
+            if (nfull == 0) load(kb, ac, bc);
+            if (kin == 3) {
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t v = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += v;
+                for (int b = 0; b < RB; ++b) ac[b] = f4{0.f, 0.f, 0.f, 0.f};
             }
-            const uint32_t total = __shfl(incl, 63, 64);
-            u64 base = 0;
-            if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
-            base = __shfl(base, 0, 64);
-            u64 slot = base + (incl - mine);
-            for (int e = 0; e < 16; ++e) {
-                if (!((umask >> e) & 1u)) continue;
-                const int64_t grow = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
-                const float p = acc[e >> 2][t][e & 3];
-                if (slot < a.list_cap) {
-                    a.list[slot] = (u64)(uint32_t)grow | ((u64)cp << 32) | ((p > 0.f) ? (1ull << 63) : 0ull);
-                } else {
-                    // Queue full: decide here (same FP64 sum as the FP64 pass).
-                    const float* xr = a.X + grow * (int64_t)a.d;
-                    const float* wr = a.Wt + (int64_t)cp * a.DP;
-                    double sacc = 0.0;
-                    for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
-                    n_ref += 1u;
-                    n_flip += ((sacc > 0.0) != (p > 0.f)) ? 1u : 0u;
-                    acc[e >> 2][t][e & 3] = sacc > 0.0 ? 1.f : -1.f;
-                }
-                ++slot;
-            }
-        }
-        uint32_t code = 0;
+            step(ac, bc);
+        } else if constexpr (REM == 8) {
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            const uint32_t kof = (uint32_t)(kb + 2 * kin) * 4u;
+            f2 av[RB], bv[TW];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
-                                            __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
-            code = (kin == b) ? cb : code;
+            for (int b = 0; b < RB; ++b)
+                av[b] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xs, xo + kof, b * xstep, 0));
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+                bv[t] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ws, wo + kof, t * wstep, 0));
+#pragma unroll
+            for (int b = 0; b < RB; ++b) ss[b] = fmaf(av[b][1], av[b][1], fmaf(av[b][0], av[b][0], ss[b]));
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int t = 0; t < TW; ++t)
+#pragma unroll
+                    for (int b = 0; b < RB; ++b)
+                        acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b][q], bv[t][q], acc[b][t], 0, 0, 0);
+        } else if constexpr (REM == 4) {
+            const uint32_t kof = (uint32_t)(kb + kin) * 4u;
+            float av[RB], bv[TW];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                av[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, xo + kof, b * xstep, 0));
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+                bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ws, wo + kof, t * wstep, 0));
+#pragma unroll
+            for (int b = 0; b < RB; ++b) ss[b] = fmaf(av[b], av[b], ss[b]);
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], bv[t], acc[b][t], 0, 0, 0);
         }
-        if (table < a.L && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
-    }
-    if (__any(n_ref != 0 || n_unc != 0)) {
-        const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip), uc = wave_sum_u32(n_unc);
-        if (lane == 0) {
-            if (r) atomicAdd(&a.counters[0], (u64)r);
-            if (f) atomicAdd(&a.counters[1], (u64)f);
-            if (uc) atomicAdd(&a.counters[2], (u64)uc);
+
+        // The next tile of this wave; the rows of its first k block are in flight during
+        // the epilogue (the W^T block, an L2 hit, is loaded after it).
+        int64_t v2 = v + gridDim.x, rbase2 = 0;
+        int cbase2 = 0;
+        while (v2 < n_slots && !slot_tile(v2, rbase2, cbase2)) v2 += gridDim.x;
+        const bool more = v2 < n_slots;
+        if (more) {
+            xs = x_view(rbase2);
+            ws = w_view(cbase2);
+            if (nfull > 0) load_a(0, ac);
         }
+
+        // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
+        // row 16b + cl, lane l needs rows 16b + 4 kin + r.
+        float rbnd[4 * RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            double s2 = (double)ss[b];
+            s2 += __shfl_xor(s2, 16, 64);
+            s2 += __shfl_xor(s2, 32, 64);
+            const float rb = (float)(a.gx * sqrt(s2 * (double)a.norm_up + (double)(d + 16) * 0x1p-125) * (1.0 + 0x1p-20));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = __shfl(rb, 4 * kin + r, 64);
+        }
+        float wcol[TW];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
+        sign_epilogue<TW, RB>(a, acc, rbnd, wcol, rbase, cbase, nv, lane);
+        if (!more) break;
+        v = v2;
+        rbase = rbase2;
+        cbase = cbase2;
     }
 }
 
@@ -301,10 +535,45 @@ __global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
     }
 }
 
+// Compute units of the current device (cached per device).
+int cu_count() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 template <int TW>
 hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
     const int64_t groups = (a.n_tiles_m + 7) / 8;
     const int64_t blocks = groups * 8 * a.n_tiles_n;
+    // The direct kernel addresses a wave's 64 rows and 16 TW columns with 32-bit byte offsets;
+    // at TW = 8 its accumulators and two operand blocks would not fit in 256 registers.
+    if constexpr (TW <= 5) {
+        if (vec && (int64_t)a.d * 64 * 4 < ((int64_t)1 << 31) && (int64_t)a.DP * 16 * TW * 4 < ((int64_t)1 << 31)) {
+            // Workgroups of 4 waves over 32 RB rows x 32 TW columns; as many resident
+            // workgroups as the register budget allows (8 / RB per CU), rounded up to a
+            // multiple of the 8 XCDs.
+            constexpr int RB = DIRECT_RB;
+            const int64_t tiles_m = (a.n + 32 * RB - 1) / (32 * RB);
+            const int64_t slots = (tiles_m + 7) / 8 * 8 * a.n_tiles_n;
+            const int64_t persist = ((int64_t)cu_count() * DIRECT_WAVES + 7) / 8 * 8;
+            const int64_t grid = slots < persist ? slots : persist;
+            const dim3 g((unsigned)grid), b(256);
+            switch (a.d & 15) {
+                case 0: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 0>), g, b, 0, s, a, tiles_m, slots); break;
+                case 4: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 4>), g, b, 0, s, a, tiles_m, slots); break;
+                case 8: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 8>), g, b, 0, s, a, tiles_m, slots); break;
+                default: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 12>), g, b, 0, s, a, tiles_m, slots); break;
+            }
+            return hipGetLastError();
+        }
+    }
     if (vec)
         hipLaunchKernelGGL((hash_fp32_kernel<TW, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     else

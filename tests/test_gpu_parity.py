@@ -43,6 +43,9 @@ def test_parity_small_clusters():
 @pytest.mark.parametrize("n,d,K,L", [
     (1, 5, 1, 1), (127, 33, 15, 3), (129, 120, 15, 50), (300, 7, 16, 4), (1000, 64, 10, 64),
     (777, 1, 4, 100), (2048, 32, 12, 9), (515, 130, 16, 13),
+    # d % 4 == 0 with every remainder of d mod 16 (last k block of 4, 8 or 12 values, d < 16)
+    (300, 4, 8, 5), (257, 8, 15, 21), (130, 12, 16, 3), (333, 100, 15, 10), (200, 24, 13, 30),
+    (64, 44, 16, 7), (1100, 16, 15, 50),
 ])
 def test_parity_shapes(n, d, K, L):
     X, _ = gaussian_clusters(n, d, 3, 0.05, seed=n + d)
