@@ -224,6 +224,7 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
     a.n_tiles_n = c->n_tiles_n;
     a.n_tiles_m = (n + 127) / 128;
     a.gx = c->gx;
+    a.gx_split = c->gx_split;
     a.eps_abs = c->eps_abs;
     a.refine = c->cfg.refine;
     a.codes = w->codes;
@@ -231,6 +232,7 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
     a.list = w->list;
     a.list_count = w->list_count;
     a.list_cap = c->list_cap < w->list_alloc ? c->list_cap : w->list_alloc;
+    a.refined = want_refined ? w->refined : nullptr;
     a.counters = c->rcnt;
     a.Wh = c->Wh;
     a.Wl = c->Wl;
@@ -442,11 +444,16 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
     // FP32 bound factor gamma_h(u), rounded up by a relative 2^-16 for the FP32 bound product:
     //   measured model: exact products, one round-to-nearest per product added -> h = DP + 4, u = 2^-24
     //   generic model:  up to 6 units of 2^-23 per 4-product instruction        -> h = 2 DP + 8, u = 2^-23
+    // The split-k kernel's chains hold at most P = 16 ceil(nfull / 4) + 16 products, and the
+    // four partial sums are added in two more roundings: h = P + 6 (measured), 2 P + 10 (generic).
     {
         const bool gen = cfg->bound_model == ACE_BOUND_GENERIC;
         const double u = ldexp(1.0, gen ? -23 : -24);
         const double h = gen ? 2.0 * c->DP + 8.0 : (double)c->DP + 4.0;
         c->gx = (float)(h * u / (1.0 - h * u) * (1.0 + ldexp(1.0, -16)));
+        const double P = 16.0 * (double)(((d >> 4) + 3) / 4) + 16.0;
+        const double hs = gen ? 2.0 * P + 10.0 : P + 6.0;
+        c->gx_split = (float)(hs * u / (1.0 - hs * u) * (1.0 + ldexp(1.0, -16)));
         c->eps_abs = (float)((2.0 * c->DP + 8.0) * ldexp(1.0, -125));
     }
     c->ws_rows = c->cfg.max_batch_rows;

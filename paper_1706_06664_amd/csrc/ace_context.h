@@ -32,6 +32,7 @@ struct ace_ctx_s {
     int NP = 0;            // padded columns allocated (n_tiles_n * 32 * TW)
     int DP = 0;            // padded contraction length
     float gx = 0.f, eps_abs = 0.f;
+    float gx_split = 0.f;                     // bound factor of the split-k FP32 kernel
 
     float* Wt = nullptr;   // [NP][DP]
     float* wb = nullptr;   // [NP]

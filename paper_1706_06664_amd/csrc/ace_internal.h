@@ -18,6 +18,10 @@ typedef __int128 i128;
 constexpr int KPAD = 16;
 // Contraction padding of the device copy of W.
 constexpr int DPAD = 32;
+// FP32 rows with at least this many 16-wide k blocks are hashed with the k range split four
+// ways over the waves of a workgroup: each accumulation chain is a quarter as long, and so
+// is the error bound (fewer projections to refine).
+constexpr int SPLIT_K_BLOCKS = 128;
 
 // Arguments of the projection + sign-pack kernels (one per precision).
 struct HashArgs {
@@ -31,6 +35,7 @@ struct HashArgs {
     int32_t n_tiles_n;     // column tiles (each 32*TW padded columns)
     int64_t n_tiles_m;     // row tiles
     float gx;              // row bound factor: gamma * safety
+    float gx_split;        // the same for the four-way split-k FP32 kernel (d >= 16 SPLIT_K_BLOCKS)
     float eps_abs;         // absolute term for flushed subnormals
     int32_t refine;
     uint16_t* codes;       // [L][ldc]: code of row i of this chunk in table j at j*ldc + i
@@ -40,6 +45,7 @@ struct HashArgs {
     u64 list_cap;
     u64* counters;         // [0] bits refined, [1] refined bits that flipped (queue-full path),
                            // [2] bits inside the bound left unrefined (refine = 2)
+    uint16_t* refined;     // [L][ldc] or null: bits decided in place (queue full) are marked
     // Split-BF16 operands and bound factors (BF16 kernel only)
     const uint16_t* Wh;    // [NP][DP] bf16 bits of w_h
     const uint16_t* Wl;    // [NP][DP] bf16 bits of w_l
@@ -81,6 +87,15 @@ struct RefineArgs {
     u64 list_cap;
     u64* counters;         // [0] bits refined, [1] refined bits that flipped
 };
+
+// Mark bit cp (padded column) of row `row` in the refined mask, if one was asked for
+// (used where a projection epilogue decides a bit itself because the queue is full).
+__device__ inline void mark_refined(const HashArgs& a, int64_t row, int cp) {
+    const int table = cp >> 4, k = cp & 15;
+    if (!a.refined || table >= a.L || k >= a.K) return;
+    const uintptr_t ra = reinterpret_cast<uintptr_t>(a.refined + (size_t)table * a.ldc + row);
+    atomicOr(reinterpret_cast<uint32_t*>(ra & ~(uintptr_t)3), 1u << (k + ((ra & 2) ? 16 : 0)));
+}
 
 // Device-side threshold result (mirrors ace_thresh).
 struct DevThresh {

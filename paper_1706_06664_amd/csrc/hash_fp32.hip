@@ -56,13 +56,15 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 
 // Epilogue shared by the projection kernels.  acc[b][t] (b < RB) is the 16x16 MFMA tile of
 // rows rbase + 16b .. and padded columns cbase + 16t ..; lane l holds rows 16b + 4(l/16) + r
-// (r = 0..3) of column l%16.  rbnd[4b + r] is the row bound factor of that row and wcol[t]
+// (r = 0..3) of column l%16; only tables t with bit t of tmask are finished here.
+// rbnd[4b + r] is the row bound factor of that row and wcol[t]
 // the column factor of this lane's column in tile t.  Projections inside their bound are
 // queued for the FP64 pass (or decided here when the queue is full); each 16-column tile
 // is one table, whose bits are gathered with ballots and stored as one uint16 per row.
 template <int TW, int RB>
 __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const float (&rbnd)[4 * RB],
-                                     const float (&wcol)[TW], int64_t rbase, int cbase, int64_t nv, int lane) {
+                                     const float (&wcol)[TW], int64_t rbase, int cbase, int64_t nv, int lane,
+                                     uint32_t tmask = ~0u) {
     const int kin = lane >> 4, cl = lane & 15;
     uint32_t rok = 0;
 #pragma unroll
@@ -72,6 +74,7 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
+        if (!((tmask >> t) & 1u)) continue;  // a table another wave finishes
         const int table = (cbase >> 4) + t;
         const int cp = cbase + t * 16 + cl;
         const float wbv = wcol[t];
@@ -118,6 +121,7 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
                     const float* wr = a.Wt + (int64_t)cp * a.DP;
                     double sacc = 0.0;
                     for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
+                    mark_refined(a, grow, cp);
                     n_ref += 1u;
                     n_flip += ((sacc > 0.0) != raw) ? 1u : 0u;
                     pos = sacc > 0.0 ? (pos | (1u << e)) : (pos & ~(1u << e));
@@ -282,26 +286,32 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
 // multiply-add, at most d/4 + 3 of them); the four k groups are added in FP64.  The sum is
 // scaled by norm_up = 1 + (DP + 2) 2^-23 >= 1 + gamma_{d/4+3}(2^-24), and (d + 16) 2^-125
 // is added for squares lost below the normal range: an upper bound of ||x||^2.
-template <int TW, int RB, int REM>
+template <int TW, int RB, int REM, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVES, DIRECT_WAVES))) void hash_fp32_direct_kernel(
     const HashArgs a, int64_t tiles_m, int64_t n_slots) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: buffer views in SGPRs
-    const int wm = wave >> 1, wn = wave & 1;
+    // KS == 1: the waves split the workgroup tile 2 (rows) x 2 (columns).  KS == 4: all four
+    // waves take the same 16 RB x 16 TW tile and a quarter of k each (kw).
+    const int wm = KS == 1 ? wave >> 1 : 0, wn = KS == 1 ? wave & 1 : 0, kw = KS == 1 ? 0 : wave;
     const int64_t nv = a.n_dev ? *a.n_dev : a.n;
     const int cl = lane & 15, kin = lane >> 4;
     const int d = a.d;
     const uint32_t xo = (uint32_t)(cl * d) * 4u, wo = (uint32_t)(cl * a.DP) * 4u;
     const int xstep = 16 * d * 4, wstep = 16 * a.DP * 4;  // bytes per 16-row / 16-column tile
     const int nfull = d >> 4;  // full 16-wide k blocks; REM = d - 16 nfull (0, 4, 8 or 12)
+    const int kb0 = nfull * kw / KS, kb1 = nfull * (kw + 1) / KS;  // this wave's full blocks
+    const float gx = KS == 1 ? a.gx : a.gx_split;
 
     // Tile slot -> this wave's first row and first padded column; false if it has no rows.
     auto slot_tile = [&](int64_t v, int64_t& rbase, int& cbase) -> bool {
+        constexpr int TR = KS == 1 ? 32 * RB : 16 * RB, TC = KS == 1 ? 32 * TW : 16 * TW;
+        const int64_t ntn = KS == 1 ? a.n_tiles_n : 2 * a.n_tiles_n;
         const int64_t xcd = v & 7, local = v >> 3;
-        const int64_t tile_n = local % a.n_tiles_n;
-        const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
-        rbase = tile_m * (32 * RB) + wm * (16 * RB);
-        cbase = (int)tile_n * 32 * TW + wn * TW * 16;
+        const int64_t tile_n = local % ntn;
+        const int64_t tile_m = (local / ntn) * 8 + xcd;
+        rbase = tile_m * TR + wm * (16 * RB);
+        cbase = (int)tile_n * TC + wn * TW * 16;
         return tile_m < tiles_m && rbase < a.n;
     };
     // Range-checked buffer views: the wave's rows of X (rows past n read as zero) and its
@@ -356,9 +366,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
     };
 
     f4 ac[RB], bc[TW];
-    if (nfull > 0) load_a(0, ac);
+    if (kb1 > kb0) load_a(16 * kb0, ac);
     for (;;) {
-        if (nfull > 0) load_b(0, bc);
+        if (kb1 > kb0) load_b(16 * kb0, bc);
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             ss[b] = 0.f;
@@ -369,8 +379,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         // operand registers alternate without copies.  Past the last full block the loads
         // read the partial block or the next rows and columns: in range, and unused unless
         // REM == 12, whose partial block it is.
-        int i = 0;
-        for (; i + 2 <= nfull; i += 2) {
+        int i = kb0;
+        for (; i + 2 <= kb1; i += 2) {
             f4 an[RB], bn[TW];
             load(16 * (i + 1), an, bn);
             step(ac, bc);
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             step(an, bn);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (i < nfull) {
+        if (i < kb1) {
             f4 an[RB], bn[TW];
             load(16 * (i + 1), an, bn);
             step(ac, bc);
@@ -393,10 +403,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             }
         }
 
+        // The partial block belongs to the last k quarter; the other quarters multiply
+        // zeros there (adding an exact zero leaves the accumulator unchanged).
         const int kb = 16 * nfull;
+        const bool tail_zero = kw != KS - 1;
         if constexpr (REM == 12) {
-            if (nfull == 0) load(kb, ac, bc);
-            if (kin == 3) {
+            if (kb1 == kb0) load(kb, ac, bc);
+            if (kin == 3 || tail_zero) {
 #pragma unroll
                 for (int b = 0; b < RB; ++b) ac[b] = f4{0.f, 0.f, 0.f, 0.f};
             }
@@ -406,8 +419,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             const uint32_t kof = (uint32_t)(kb + 2 * kin) * 4u;
             f2 av[RB], bv[TW];
 #pragma unroll
-            for (int b = 0; b < RB; ++b)
+            for (int b = 0; b < RB; ++b) {
                 av[b] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xs, xo + kof, b * xstep, 0));
+                if (tail_zero) av[b] = f2{0.f, 0.f};
+            }
 #pragma unroll
             for (int t = 0; t < TW; ++t)
                 bv[t] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ws, wo + kof, t * wstep, 0));
@@ -424,8 +439,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             const uint32_t kof = (uint32_t)(kb + kin) * 4u;
             float av[RB], bv[TW];
 #pragma unroll
-            for (int b = 0; b < RB; ++b)
+            for (int b = 0; b < RB; ++b) {
                 av[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, xo + kof, b * xstep, 0));
+                if (tail_zero) av[b] = 0.f;
+            }
 #pragma unroll
             for (int t = 0; t < TW; ++t)
                 bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ws, wo + kof, t * wstep, 0));
@@ -447,9 +464,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         if (more) {
             xs = x_view(rbase2);
             ws = w_view(cbase2);
-            if (nfull > 0) load_a(0, ac);
+            if (kb1 > kb0) load_a(16 * kb0, ac);
         }
 
+        uint32_t tmask = ~0u;
+        if constexpr (KS == 4) {
+            // Table t of the tile is finished by wave t % 4.  The other three waves hand it
+            // their partial sums through LDS; it adds the four as (q0 + q1) + (q2 + q3), in
+            // k order whichever wave it is.  Every wave needs the whole row norm.  The first
+            // barrier keeps the previous tile's partials until they have been read.
+            __shared__ f4 part[TW][3][RB][64];
+            __shared__ f4 spart[4][64];
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < TW; ++t) {
+                const int o = t & 3;
+                if (o != kw) {
+                    const int sl = kw - (kw > o ? 1 : 0);
+#pragma unroll
+                    for (int b = 0; b < RB; ++b) part[t][sl][b][lane] = acc[b][t];
+                }
+            }
+            {
+                f4 sv = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < RB; ++b) sv[b] = ss[b];
+                spart[kw][lane] = sv;
+            }
+            __syncthreads();
+            tmask = 0u;
+#pragma unroll
+            for (int t = 0; t < TW; ++t) {
+                if ((t & 3) != kw) continue;
+                tmask |= 1u << t;
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    f4 q[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) q[w] = (w == kw) ? acc[b][t] : part[t][w - (w > kw ? 1 : 0)][b][lane];
+                    acc[b][t] = (q[0] + q[1]) + (q[2] + q[3]);
+                    __builtin_amdgcn_sched_barrier(0);  // one tile at a time: few registers in flight
+                }
+            }
+            const f4 s0 = spart[0][lane], s1 = spart[1][lane], s2 = spart[2][lane], s3 = spart[3][lane];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) ss[b] = (s0[b] + s1[b]) + (s2[b] + s3[b]);
+        }
         // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
         // row 16b + cl, lane l needs rows 16b + 4 kin + r.
         float rbnd[4 * RB];
@@ -458,14 +518,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             double s2 = (double)ss[b];
             s2 += __shfl_xor(s2, 16, 64);
             s2 += __shfl_xor(s2, 32, 64);
-            const float rb = (float)(a.gx * sqrt(s2 * (double)a.norm_up + (double)(d + 16) * 0x1p-125) * (1.0 + 0x1p-20));
+            const float rb = (float)(gx * sqrt(s2 * (double)a.norm_up + (double)(d + 16) * 0x1p-125) * (1.0 + 0x1p-20));
 #pragma unroll
             for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = __shfl(rb, 4 * kin + r, 64);
         }
         float wcol[TW];
 #pragma unroll
         for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
-        sign_epilogue<TW, RB>(a, acc, rbnd, wcol, rbase, cbase, nv, lane);
+        sign_epilogue<TW, RB>(a, acc, rbnd, wcol, rbase, cbase, nv, lane, tmask);
         if (!more) break;
         v = v2;
         rbase = rbase2;
@@ -548,6 +608,94 @@ int cu_count() {
     return cus[dev];
 }
 
+// FP64 pass, staged variant (16-byte aligned rows, d % 4 == 0).  A wave takes 64 queue
+// entries, one per lane, and walks k in chunks of 32: the wave loads the chunk of every
+// entry's row and column with 16-byte loads (eight lanes per entry, so each load
+// instruction reads eight whole 128-byte segments), parks them in LDS, and then every lane
+// runs its entry's FP64 sum over the chunk in ascending t.  The sum and the bit patch are
+// those of refine_kernel; only the memory access pattern differs.  All waves of a block
+// step through the same chunks, so the block-wide barriers match.
+constexpr int RC = 32;        // k per chunk
+constexpr int RS = RC + 1;    // LDS row stride in floats (lane e reads row e: distinct banks)
+
+__global__ __launch_bounds__(256, 2) void refine_staged_kernel(const RefineArgs a) {
+    __shared__ float xs[4][64 * RS], ws[4][64 * RS];
+    const u64 n_ent = min(*a.list_count, a.list_cap);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int d = a.d;
+    float* xw = xs[wave];
+    float* ww = ws[wave];
+    uint32_t n_ref = 0, n_flip = 0;
+    for (u64 g0 = (u64)blockIdx.x * 256; g0 < n_ent; g0 += (u64)gridDim.x * 256) {
+        const u64 i = g0 + (u64)threadIdx.x;
+        const bool ok = i < n_ent;
+        const u64 e = ok ? a.list[i] : 0ull;
+        const int64_t row = (int64_t)(e & 0xFFFFFFFFull);
+        const int cp = (int)((e >> 32) & 0xFFFFu);
+        double s = 0.0;
+        for (int t0 = 0; t0 < d; t0 += RC) {
+            // Lane l stages 4 values of entry 8j + l/8 (j = 0..7) at t0 + 4 (l % 8).
+            const int q = 4 * (lane & 7);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int ee = 8 * j + (lane >> 3);
+                const int64_t er = __shfl(row, ee, 64);
+                const int ec = __shfl(cp, ee, 64);
+                const bool eok = g0 + (u64)(64 * wave + ee) < n_ent;
+                f4 xv = f4{0.f, 0.f, 0.f, 0.f}, wv = f4{0.f, 0.f, 0.f, 0.f};
+                if (eok) {
+                    const float* xr = a.X + er * (int64_t)d + t0 + q;
+                    if (t0 + q + 4 <= d) {
+                        xv = *reinterpret_cast<const f4*>(xr);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) xv[u] = (t0 + q + u < d) ? xr[u] : 0.f;
+                    }
+                    // W^T rows are zero-padded to DP, a multiple of the chunk size.
+                    wv = *reinterpret_cast<const f4*>(a.Wt + (int64_t)ec * a.DP + t0 + q);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xw[ee * RS + q + u] = xv[u];
+                    ww[ee * RS + q + u] = wv[u];
+                }
+            }
+            __syncthreads();
+            // Past d the staged values are zeros: adding an exact zero leaves the sum's
+            // value unchanged (at most -0 becomes +0, which is not > 0 either way).
+#pragma unroll 8
+            for (int t = 0; t < RC; ++t) s = fma((double)xw[lane * RS + t], (double)ww[lane * RS + t], s);
+            __syncthreads();
+        }
+        if (ok) {
+            const bool raw = (e >> 63) != 0;
+            const bool bit = s > 0.0;
+            const int table = cp >> 4, k = cp & 15;
+            if (table < a.L && k < a.K) {
+                const size_t idx = (size_t)table * a.ldc + row;
+                const uintptr_t addr = reinterpret_cast<uintptr_t>(a.codes + idx);
+                uint32_t* word = reinterpret_cast<uint32_t*>(addr & ~(uintptr_t)3);
+                const uint32_t m = 1u << (k + ((addr & 2) ? 16 : 0));
+                if (bit != raw) {
+                    if (bit) atomicOr(word, m);
+                    else atomicAnd(word, ~m);
+                }
+                if (a.refined) {
+                    const uintptr_t ra = reinterpret_cast<uintptr_t>(a.refined + idx);
+                    atomicOr(reinterpret_cast<uint32_t*>(ra & ~(uintptr_t)3), 1u << (k + ((ra & 2) ? 16 : 0)));
+                }
+                n_ref += 1u;
+                n_flip += (bit != raw) ? 1u : 0u;
+            }
+        }
+    }
+    const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
+    if (lane == 0 && r) {
+        atomicAdd(&a.counters[0], (u64)r);
+        if (f) atomicAdd(&a.counters[1], (u64)f);
+    }
+}
+
 template <int TW>
 hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
     const int64_t groups = (a.n_tiles_m + 7) / 8;
@@ -556,20 +704,33 @@ hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
     // at TW = 8 its accumulators and two operand blocks would not fit in 256 registers.
     if constexpr (TW <= 5) {
         if (vec && (int64_t)a.d * 64 * 4 < ((int64_t)1 << 31) && (int64_t)a.DP * 16 * TW * 4 < ((int64_t)1 << 31)) {
-            // Workgroups of 4 waves over 32 RB rows x 32 TW columns; as many resident
-            // workgroups as the register budget allows (8 / RB per CU), rounded up to a
-            // multiple of the 8 XCDs.
             constexpr int RB = DIRECT_RB;
+            const dim3 b(256);
+            // Two resident workgroups per CU, rounded up to a multiple of the 8 XCDs.
+            const int64_t persist = ((int64_t)cu_count() * DIRECT_WAVES + 7) / 8 * 8;
+            if ((a.d >> 4) >= SPLIT_K_BLOCKS) {
+                // Long rows: workgroups of 4 waves over 16 RB rows x 16 TW columns, k split
+                // four ways (a quarter of the accumulation chain per wave: a 4x tighter bound).
+                const int64_t tiles_m = (a.n + 16 * RB - 1) / (16 * RB);
+                const int64_t slots = (tiles_m + 7) / 8 * 8 * (2 * a.n_tiles_n);
+                const dim3 g((unsigned)(slots < persist ? slots : persist));
+                switch (a.d & 15) {
+                    case 0: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 0, 4>), g, b, 0, s, a, tiles_m, slots); break;
+                    case 4: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 4, 4>), g, b, 0, s, a, tiles_m, slots); break;
+                    case 8: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 8, 4>), g, b, 0, s, a, tiles_m, slots); break;
+                    default: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 12, 4>), g, b, 0, s, a, tiles_m, slots); break;
+                }
+                return hipGetLastError();
+            }
+            // Workgroups of 4 waves over 32 RB rows x 32 TW columns.
             const int64_t tiles_m = (a.n + 32 * RB - 1) / (32 * RB);
             const int64_t slots = (tiles_m + 7) / 8 * 8 * a.n_tiles_n;
-            const int64_t persist = ((int64_t)cu_count() * DIRECT_WAVES + 7) / 8 * 8;
-            const int64_t grid = slots < persist ? slots : persist;
-            const dim3 g((unsigned)grid), b(256);
+            const dim3 g((unsigned)(slots < persist ? slots : persist));
             switch (a.d & 15) {
-                case 0: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 0>), g, b, 0, s, a, tiles_m, slots); break;
-                case 4: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 4>), g, b, 0, s, a, tiles_m, slots); break;
-                case 8: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 8>), g, b, 0, s, a, tiles_m, slots); break;
-                default: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 12>), g, b, 0, s, a, tiles_m, slots); break;
+                case 0: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 0, 1>), g, b, 0, s, a, tiles_m, slots); break;
+                case 4: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 4, 1>), g, b, 0, s, a, tiles_m, slots); break;
+                case 8: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 8, 1>), g, b, 0, s, a, tiles_m, slots); break;
+                default: hipLaunchKernelGGL((hash_fp32_direct_kernel<TW, RB, 12, 1>), g, b, 0, s, a, tiles_m, slots); break;
             }
             return hipGetLastError();
         }
@@ -585,6 +746,13 @@ hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
 
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s) {
     int64_t blocks = (max_entries + 255) / 256;
+    if (vec && a.DP % RC == 0) {
+        const int64_t resident = (int64_t)cu_count() * 2;
+        if (blocks > resident) blocks = resident;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(refine_staged_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     if (vec)

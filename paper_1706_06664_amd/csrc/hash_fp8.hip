@@ -275,6 +275,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
                     const float* wr = a.Wt + (int64_t)cp * a.DP;
                     double sacc = 0.0;
                     for (int u = 0; u < a.d; ++u) sacc += (double)xr[u] * (double)wr[u];
+                    mark_refined(a, grow, cp);
                     n_ref += 1u;
                     n_flip += ((sacc > 0.0) != (pv > 0.f)) ? 1u : 0u;
                     acc[e >> 2][t][e & 3] = sacc > 0.0 ? 1.f : -1.f;

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256) void hash_struct_kernel(const HashArgs a) {
                         const float* wr = a.Wt + (int64_t)cp * a.DP;
                         double s = 0.0;
                         for (int t = 0; t < a.d; ++t) s += (double)xr[t] * (double)wr[t];
+                        mark_refined(a, row, cp);
                         n_ref += 1u;
                         n_flip += ((s > 0.0) != raw) ? 1u : 0u;
                         if (s > 0.0) bits[i] |= 1ull << bpos;

@@ -145,10 +145,18 @@ def adversarial_rows(X: np.ndarray, W: np.ndarray, n_near: int, n_cancel: int, s
 
 
 def fp32_bound(X: np.ndarray, W: np.ndarray, model: str) -> np.ndarray:
-    """The FP32-mode refinement bound gamma_h(u) ||x|| ||w|| the library states."""
+    """The FP32-mode refinement bound gamma_h(u) ||x|| ||w|| the library states.  Rows of
+    2048 or more values (128 or more 16-wide k blocks) are hashed with k split four ways:
+    chains of at most P = 16 ceil(nfull/4) + 16 products plus two roundings to add the
+    four partial sums."""
     d = X.shape[1]
     DP = -(-d // 32) * 32
-    h, u = (2 * DP + 8, 2.0 ** -23) if model == "generic" else (DP + 4, 2.0 ** -24)
+    nfull = d // 16
+    if nfull >= 128:
+        P = 16 * (-(-nfull // 4)) + 16
+        h, u = (2 * P + 10, 2.0 ** -23) if model == "generic" else (P + 6, 2.0 ** -24)
+    else:
+        h, u = (2 * DP + 8, 2.0 ** -23) if model == "generic" else (DP + 4, 2.0 ** -24)
     gam = h * u / (1 - h * u)
     return gam * np.linalg.norm(X.astype(np.float64), axis=1)[:, None] * \
         np.linalg.norm(W.astype(np.float64), axis=0)[None, :]

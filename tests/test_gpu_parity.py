@@ -46,6 +46,8 @@ def test_parity_small_clusters():
     # d % 4 == 0 with every remainder of d mod 16 (last k block of 4, 8 or 12 values, d < 16)
     (300, 4, 8, 5), (257, 8, 15, 21), (130, 12, 16, 3), (333, 100, 15, 10), (200, 24, 13, 30),
     (64, 44, 16, 7), (1100, 16, 15, 50),
+    # 128+ k blocks: k split four ways over a workgroup's waves (every d mod 16 remainder)
+    (300, 2048, 15, 11), (257, 2052, 16, 9), (129, 2056, 12, 13), (200, 2060, 16, 5), (70, 4100, 16, 20),
 ])
 def test_parity_shapes(n, d, K, L):
     X, _ = gaussian_clusters(n, d, 3, 0.05, seed=n + d)
@@ -94,14 +96,20 @@ def test_zero_rows_identical_rows_near_orthogonal():
 
 
 @pytest.mark.parametrize("model", ["measured", "generic"])
-def test_refine_off_respects_bound(model):
+@pytest.mark.parametrize("long_rows", [False, True], ids=["d120", "d2056_split_k"])
+def test_refine_off_respects_bound(model, long_rows):
     """Raw FP32 MFMA signs (refine off) may differ from the FP64 signs only where |p64|
-    is inside the library's stated FP32 bound for the error model."""
+    is inside the library's stated FP32 bound for the error model (for 2056-wide rows, the
+    bound of the split-k kernel)."""
     import torch
     from paper_1706_06664_amd import ACE, codes_as_uint16
     from tests.parity import adversarial_rows, fp32_bound, raw_flip_report
-    K, L = 15, 50
-    X0, _ = c2_points(n=4000, seed=8)
+    if long_rows:
+        K, L = 16, 20
+        X0, _ = gaussian_clusters(1500, 2056, 4, 0.3, seed=8)
+    else:
+        K, L = 15, 50
+        X0, _ = c2_points(n=4000, seed=8)
     W = projection_matrix(X0.shape[1], K, L, 4)
     X = adversarial_rows(X0, W, 3000, 3000, seed=8)
     ace = ACE(W, K, L, refine=False, bound=model)
@@ -228,9 +236,9 @@ def test_refine_queue_full_path():
         cg = codes_as_uint16(cg)
         bad, _, _ = compare_codes(cg, co, amb)
         assert bad == 0
-        res.append((cg, ace.counters()["bits_refined"]))
-        if q == 0:
-            refm = codes_as_uint16(ref)
-            assert np.all(refm[:64] == (1 << K) - 1)      # zero rows: every bit refined
+        res.append((cg, ace.counters()["bits_refined"], codes_as_uint16(ref)))
+        # zero rows: every bit refined, and marked so whether queued or decided in place
+        assert np.all(res[-1][2][:64] == (1 << K) - 1)
     assert np.array_equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1] and res[0][1] >= 64 * K * L
+    assert np.array_equal(res[0][2], res[1][2])
