@@ -122,3 +122,28 @@ def test_bf16_raw_signs_stay_inside_stated_bound(model, shape):
     rep = raw_flip_report(cg, P, bf16_bound(X, W, model), K, L)
     _say(rep)
     assert rep["violations"] == 0
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_chunked_conversion(precision):
+    """Several chunks (max_batch_rows = 1000, ragged last chunk), each converted and hashed in
+    turn.  Hash, insert, score and flags must match the oracle as for one chunk, for aligned
+    rows and for an unaligned view (scalar loads)."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    X, _ = gaussian_clusters(3500, 96, 4, 0.05, seed=21)
+    W = projection_matrix(96, 15, 20, 22)
+    r = full_parity(X, W, 15, 20, precision=precision, max_batch_rows=1000)
+    _say(r)
+    big = torch.from_numpy(np.concatenate([np.zeros(1, np.float32), X.ravel()])).cuda()
+    Xoff = big[1:].view(3500, 96)
+    assert Xoff.data_ptr() % 16 != 0
+    ace = ACE(W, 15, 20, precision=precision, max_batch_rows=1000)
+    cg = codes_as_uint16(ace.hash(Xoff))
+    co, amb = oracle.hash_codes(X, W, 15, 20)
+    bad, _, _ = compare_codes(cg, co, amb)
+    assert bad == 0
+    # the same context again: its buffers are reused across calls
+    cg2 = codes_as_uint16(ace.hash(torch.from_numpy(X).cuda()))
+    assert np.array_equal(cg, cg2)
+    ace.close()
