@@ -113,6 +113,8 @@ hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec
                               float* rowB, float norm_up, hipStream_t s);
 hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s);
 hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s);
+// Compute units of the current device (cached per device; 256 if it cannot be read).
+int cu_count();
 hipError_t launch_hash_struct(const HashArgs& a, hipStream_t s);
 hipError_t init_struct_attributes();
 // sign = +1 insert, -1 delete

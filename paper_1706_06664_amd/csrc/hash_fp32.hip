@@ -533,169 +533,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
     }
 }
 
-// FP64 pass over the queued projections.  Entry = row | column << 32 | raw bit << 63.
-// The FP64 sum runs over ascending t from the FP32 inputs; the code bit is set or
-// cleared with a 32-bit atomic on the word holding the code (the workspace is padded
-// so that word never leaves it).  refined (optional, same layout) gets the bit marked.
-template <bool VEC>
-__global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
-    const u64 n_ent = min(*a.list_count, a.list_cap);
-    uint32_t n_ref = 0, n_flip = 0;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_ent; i += (u64)gridDim.x * blockDim.x) {
-        const u64 e = a.list[i];
-        const int64_t row = (int64_t)(e & 0xFFFFFFFFull);
-        const int cp = (int)((e >> 32) & 0xFFFFu);
-        const bool raw = (e >> 63) != 0;
-        const float* xr = a.X + row * (int64_t)a.d;
-        const float* wr = a.Wt + (int64_t)cp * a.DP;
-        double s = 0.0;
-        int u = 0;
-        if (VEC) {
-            // 16-byte loads, four in flight; the additions still run in ascending t.
-            typedef float f4 __attribute__((ext_vector_type(4)));
-            for (; u + 16 <= a.d; u += 16) {
-                const f4 x0 = *reinterpret_cast<const f4*>(xr + u), w0 = *reinterpret_cast<const f4*>(wr + u);
-                const f4 x1 = *reinterpret_cast<const f4*>(xr + u + 4), w1 = *reinterpret_cast<const f4*>(wr + u + 4);
-                const f4 x2 = *reinterpret_cast<const f4*>(xr + u + 8), w2 = *reinterpret_cast<const f4*>(wr + u + 8);
-                const f4 x3 = *reinterpret_cast<const f4*>(xr + u + 12), w3 = *reinterpret_cast<const f4*>(wr + u + 12);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s += (double)x0[q] * (double)w0[q];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s += (double)x1[q] * (double)w1[q];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s += (double)x2[q] * (double)w2[q];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s += (double)x3[q] * (double)w3[q];
-            }
-        }
-        for (; u < a.d; ++u) s += (double)xr[u] * (double)wr[u];
-        const bool bit = s > 0.0;
-        const int table = cp >> 4, k = cp & 15;
-        if (table < a.L && k < a.K) {
-            const size_t idx = (size_t)table * a.ldc + row;
-            const uintptr_t addr = reinterpret_cast<uintptr_t>(a.codes + idx);
-            uint32_t* word = reinterpret_cast<uint32_t*>(addr & ~(uintptr_t)3);
-            const uint32_t m = 1u << (k + ((addr & 2) ? 16 : 0));
-            if (bit != raw) {
-                if (bit) atomicOr(word, m);
-                else atomicAnd(word, ~m);
-            }
-            if (a.refined) {
-                const uintptr_t ra = reinterpret_cast<uintptr_t>(a.refined + idx);
-                atomicOr(reinterpret_cast<uint32_t*>(ra & ~(uintptr_t)3), 1u << (k + ((ra & 2) ? 16 : 0)));
-            }
-            n_ref += 1u;
-            n_flip += (bit != raw) ? 1u : 0u;
-        }
-    }
-    const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
-    if ((threadIdx.x & 63) == 0 && r) {
-        atomicAdd(&a.counters[0], (u64)r);
-        if (f) atomicAdd(&a.counters[1], (u64)f);
-    }
-}
-
-// Compute units of the current device (cached per device).
-int cu_count() {
-    static int cus[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cus[dev] == 0) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cus[dev] = n;
-    }
-    return cus[dev];
-}
-
-// FP64 pass, staged variant (16-byte aligned rows, d % 4 == 0).  A wave takes 64 queue
-// entries, one per lane, and walks k in chunks of 32: the wave loads the chunk of every
-// entry's row and column with 16-byte loads (eight lanes per entry, so each load
-// instruction reads eight whole 128-byte segments), parks them in LDS, and then every lane
-// runs its entry's FP64 sum over the chunk in ascending t.  The sum and the bit patch are
-// those of refine_kernel; only the memory access pattern differs.  All waves of a block
-// step through the same chunks, so the block-wide barriers match.
-constexpr int RC = 32;        // k per chunk
-constexpr int RS = RC + 1;    // LDS row stride in floats (lane e reads row e: distinct banks)
-
-__global__ __launch_bounds__(256, 2) void refine_staged_kernel(const RefineArgs a) {
-    __shared__ float xs[4][64 * RS], ws[4][64 * RS];
-    const u64 n_ent = min(*a.list_count, a.list_cap);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int d = a.d;
-    float* xw = xs[wave];
-    float* ww = ws[wave];
-    uint32_t n_ref = 0, n_flip = 0;
-    for (u64 g0 = (u64)blockIdx.x * 256; g0 < n_ent; g0 += (u64)gridDim.x * 256) {
-        const u64 i = g0 + (u64)threadIdx.x;
-        const bool ok = i < n_ent;
-        const u64 e = ok ? a.list[i] : 0ull;
-        const int64_t row = (int64_t)(e & 0xFFFFFFFFull);
-        const int cp = (int)((e >> 32) & 0xFFFFu);
-        double s = 0.0;
-        for (int t0 = 0; t0 < d; t0 += RC) {
-            // Lane l stages 4 values of entry 8j + l/8 (j = 0..7) at t0 + 4 (l % 8).
-            const int q = 4 * (lane & 7);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int ee = 8 * j + (lane >> 3);
-                const int64_t er = __shfl(row, ee, 64);
-                const int ec = __shfl(cp, ee, 64);
-                const bool eok = g0 + (u64)(64 * wave + ee) < n_ent;
-                f4 xv = f4{0.f, 0.f, 0.f, 0.f}, wv = f4{0.f, 0.f, 0.f, 0.f};
-                if (eok) {
-                    const float* xr = a.X + er * (int64_t)d + t0 + q;
-                    if (t0 + q + 4 <= d) {
-                        xv = *reinterpret_cast<const f4*>(xr);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) xv[u] = (t0 + q + u < d) ? xr[u] : 0.f;
-                    }
-                    // W^T rows are zero-padded to DP, a multiple of the chunk size.
-                    wv = *reinterpret_cast<const f4*>(a.Wt + (int64_t)ec * a.DP + t0 + q);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    xw[ee * RS + q + u] = xv[u];
-                    ww[ee * RS + q + u] = wv[u];
-                }
-            }
-            __syncthreads();
-            // Past d the staged values are zeros: adding an exact zero leaves the sum's
-            // value unchanged (at most -0 becomes +0, which is not > 0 either way).
-#pragma unroll 8
-            for (int t = 0; t < RC; ++t) s = fma((double)xw[lane * RS + t], (double)ww[lane * RS + t], s);
-            __syncthreads();
-        }
-        if (ok) {
-            const bool raw = (e >> 63) != 0;
-            const bool bit = s > 0.0;
-            const int table = cp >> 4, k = cp & 15;
-            if (table < a.L && k < a.K) {
-                const size_t idx = (size_t)table * a.ldc + row;
-                const uintptr_t addr = reinterpret_cast<uintptr_t>(a.codes + idx);
-                uint32_t* word = reinterpret_cast<uint32_t*>(addr & ~(uintptr_t)3);
-                const uint32_t m = 1u << (k + ((addr & 2) ? 16 : 0));
-                if (bit != raw) {
-                    if (bit) atomicOr(word, m);
-                    else atomicAnd(word, ~m);
-                }
-                if (a.refined) {
-                    const uintptr_t ra = reinterpret_cast<uintptr_t>(a.refined + idx);
-                    atomicOr(reinterpret_cast<uint32_t*>(ra & ~(uintptr_t)3), 1u << (k + ((ra & 2) ? 16 : 0)));
-                }
-                n_ref += 1u;
-                n_flip += (bit != raw) ? 1u : 0u;
-            }
-        }
-    }
-    const uint32_t r = wave_sum_u32(n_ref), f = wave_sum_u32(n_flip);
-    if (lane == 0 && r) {
-        atomicAdd(&a.counters[0], (u64)r);
-        if (f) atomicAdd(&a.counters[1], (u64)f);
-    }
-}
-
 template <int TW>
 hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
     const int64_t groups = (a.n_tiles_m + 7) / 8;
@@ -743,24 +580,6 @@ hipError_t launch_tw(const HashArgs& a, bool vec, hipStream_t s) {
 }
 
 }  // namespace
-
-hipError_t launch_refine(const RefineArgs& a, int64_t max_entries, bool vec, hipStream_t s) {
-    int64_t blocks = (max_entries + 255) / 256;
-    if (vec && a.DP % RC == 0) {
-        const int64_t resident = (int64_t)cu_count() * 2;
-        if (blocks > resident) blocks = resident;
-        if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(refine_staged_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
-        return hipGetLastError();
-    }
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    if (vec)
-        hipLaunchKernelGGL(refine_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(refine_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
 
 hipError_t launch_hash_fp32(const HashArgs& a, int TW, bool vec, hipStream_t s) {
     switch (TW) {
