@@ -140,6 +140,54 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     }
 
 
+def cache_codes_run(Xd, W, K, L, steps, warmup):
+    """The same step with each row hashed once: hash, then insert and score from the codes
+    (ace_hash, ace_insert_codes, ace_score_codes), threshold and flags.  Reported beside the
+    headline, whose insert and score each hash the rows."""
+    import torch
+    from paper_1706_06664_amd import ACE
+    ace = ACE(W, K, L, precision="fp32", device=0)
+
+    def step():
+        ace.reset()
+        codes = ace.hash(Xd)
+        ace.insert_codes(codes)
+        _, T = ace.score_codes(codes)
+        th = ace.threshold("scored", 1.0)
+        return ace.flag(T, th["tau"], "scored")
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        flags = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ace.close()
+    return {"points_per_s": Xd.shape[0] / (ms / 1e3), "ms_per_step": ms, "flagged": int(flags.sum().item()),
+            "step": "hash once, insert codes, score codes, threshold, flags"}
+
+
+def paper_shape_runs(steps, warmup):
+    """Synthetic Gaussian-mixture rows of the shapes of the paper's three datasets (Shuttle
+    34,987 x 9, ALOI 50,000 x 27, KDD-Cup99 HTTP 596,853 x 36) at K = 15, L = 50, FP32 with
+    FP64 refine: context beside the paper's single-core times (Tables 3-5), not a like-for-like
+    comparison (different data, different machine)."""
+    import torch
+    from ace_inputs import gaussian_clusters, projection_matrix
+    out = {}
+    for name, n, d, seed, paper_s in (("shuttle_shape", 34_987, 9, 31, 0.81), ("aloi_shape", 50_000, 27, 32, 1.26),
+                                      ("kdd_http_shape", 596_853, 36, 33, 23.33)):
+        X, _ = gaussian_clusters(n, d, 8, 0.02, seed=seed)
+        W = projection_matrix(d, 15, 50, 1706066650 + seed)
+        r = run_workload(torch.from_numpy(X).to("cuda:0"), W, 15, 50, "fp32", steps, warmup)
+        out[name] = {"n": n, "d": d, "points_per_s": r["points_per_s"], "ms_per_step": r["ms_per_step"],
+                     "paper_points_per_s_cpu": n / paper_s}
+        log(f"  {name}: {r['ms_per_step']:.3f} ms/step")
+    return out
+
+
 def raw_score_error(Xs, W, K, L, precision):
     """Score error of raw low-precision signs (refinement off) against the refined scores,
     which equal the FP64 oracle's (checked by the GPU tests): insert and score the sample."""
@@ -385,6 +433,11 @@ def main():
         log("connection-log structured fp32")
         extra["connection_log_structured"] = run_workload(Xd, None, K, L, "fp32", args.steps, args.warmup, signs=s2)
         log(f"  {extra['connection_log_structured']['ms_per_step']:.3f} ms/step")
+        log("connection-log fp32, rows hashed once per step")
+        extra["connection_log_cache_codes"] = cache_codes_run(Xd, W, K, L, args.steps, args.warmup)
+        log(f"  {extra['connection_log_cache_codes']['ms_per_step']:.3f} ms/step")
+        log("paper-shape context runs")
+        extra["paper_shapes"] = paper_shape_runs(args.steps, args.warmup)
         log("connection-log fp32, 16-bit counters")
         c16 = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup, counter_bits=16)
         extra["connection_log_counters16"] = c16
