@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
     for (int k0 = 4 * lane; k0 < DP; k0 += 256) {
         f4 v;
         if (VEC && k0 + 4 <= d) {
-            v = *reinterpret_cast<const f4*>(xr + k0);
+            v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(xr + k0));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = (k0 + e < d) ? xr[k0 + e] : 0.f;
@@ -101,8 +101,9 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
             ph[e] = (short)hb;
             pl[e] = (short)lb;
         }
-        *reinterpret_cast<s4v*>(Xh + row * (int64_t)DP + k0) = ph;
-        *reinterpret_cast<s4v*>(Xl + row * (int64_t)DP + k0) = pl;
+        // streamed in and out: the projection kernel reads the split rows back much later
+        __builtin_nontemporal_store(ph, reinterpret_cast<s4v*>(Xh + row * (int64_t)DP + k0));
+        __builtin_nontemporal_store(pl, reinterpret_cast<s4v*>(Xl + row * (int64_t)DP + k0));
     }
     for (int off = 32; off > 0; off >>= 1) {
         sA += __shfl_xor(sA, off, 64);

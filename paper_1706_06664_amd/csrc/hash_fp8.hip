@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restric
             sB = fmaf(dx, dx, sB);
             word |= code << (8 * b);
         }
-        *reinterpret_cast<uint32_t*>(Xq + row * (int64_t)DP + k) = word;
+        // streamed out: the projection kernel reads the rows back much later
+        __builtin_nontemporal_store(word, reinterpret_cast<uint32_t*>(Xq + row * (int64_t)DP + k));
     };
 #pragma unroll
     for (int i = 0; i < RCACHE; ++i)
