@@ -78,23 +78,34 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
         const int table = (cbase >> 4) + t;
         const int cp = cbase + t * 16 + cl;
         const float wbv = wcol[t];
-        // Bit e of pos: sign of accumulator element e; bit e of umask: inside the bound.
-        uint32_t umask = 0, pos = 0;
+        // Bit e of umask: accumulator element e lies inside its bound.
+        uint32_t umask = 0;
         const bool chk = a.refine && wbv >= 0.f;
 #pragma unroll
         for (int e = 0; e < 4 * RB; ++e) {
-            const float p = acc[e >> 2][t][e & 3];
-            pos |= (p > 0.f) ? (1u << e) : 0u;
             const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
-            umask |= (chk && !(fabsf(p) > thr)) ? (1u << e) : 0u;  // NaN is uncertain too
+            umask |= (chk && !(fabsf(acc[e >> 2][t][e & 3]) > thr)) ? (1u << e) : 0u;  // NaN is uncertain too
         }
         umask &= rok;
         if (a.refine == 2) {
             n_unc += __popc(umask);  // count only: the raw signs stand
             umask = 0;
         }
-        if (__any(umask != 0)) {
-            // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave.
+        uint32_t code = 0;
+        if (!__any(umask != 0)) {
+            // Common case: the signs stand; ballots straight from the accumulators.
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
+                                                __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
+                code = (kin == b) ? cb : code;
+            }
+        } else {
+            // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave;
+            // bit e of pos is the sign of element e (patched where decided in place).
+            uint32_t pos = 0;
+#pragma unroll
+            for (int e = 0; e < 4 * RB; ++e) pos |= (acc[e >> 2][t][e & 3] > 0.f) ? (1u << e) : 0u;
             const uint32_t mine = __popc(umask);
             uint32_t incl = mine;
 #pragma unroll
@@ -128,14 +139,13 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
                 }
                 ++slot;
             }
-        }
-        uint32_t code = 0;
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            const uint32_t cb = select_code(__ballot((pos >> (4 * b)) & 1u), __ballot((pos >> (4 * b + 1)) & 1u),
-                                            __ballot((pos >> (4 * b + 2)) & 1u), __ballot((pos >> (4 * b + 3)) & 1u),
-                                            lane);
-            code = (kin == b) ? cb : code;
+            for (int b = 0; b < RB; ++b) {
+                const uint32_t cb = select_code(__ballot((pos >> (4 * b)) & 1u), __ballot((pos >> (4 * b + 1)) & 1u),
+                                                __ballot((pos >> (4 * b + 2)) & 1u), __ballot((pos >> (4 * b + 3)) & 1u),
+                                                lane);
+                code = (kin == b) ? cb : code;
+            }
         }
         if (table < a.L && lane < 16 * RB && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
