@@ -52,8 +52,10 @@ ace_status ws_alloc(ace_ctx c, Workspace* w, int64_t rows) {
     st = st ? st : dev_alloc(c, (void**)&w->list, sizeof(u64) * (size_t)w->list_alloc);
     st = st ? st : dev_alloc(c, (void**)&w->list_count, sizeof(u64));
     if (c->cfg.precision == ACE_BF16) {
-        st = st ? st : dev_alloc(c, (void**)&w->xh, sizeof(uint16_t) * (size_t)rows * c->DP);
-        st = st ? st : dev_alloc(c, (void**)&w->xl, sizeof(uint16_t) * (size_t)rows * c->DP);
+        // whole 16-row tiles (the convert pass zeroes the rows past the chunk's last)
+        const size_t rows16 = (size_t)(rows + 15) / 16 * 16;
+        st = st ? st : dev_alloc(c, (void**)&w->xh, sizeof(uint16_t) * rows16 * c->DP);
+        st = st ? st : dev_alloc(c, (void**)&w->xl, sizeof(uint16_t) * rows16 * c->DP);
     }
     if (c->cfg.precision == ACE_FP8E4M3) st = st ? st : dev_alloc(c, (void**)&w->xq, (size_t)rows * c->DP);
     if (c->cfg.precision != ACE_FP32) st = st ? st : dev_alloc(c, (void**)&w->rown, sizeof(float) * 3 * (size_t)rows);
@@ -539,8 +541,8 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
                     const uint16_t lb = host_bf16_bits(r1);
                     const float lv = host_bf16_val(lb);
                     const float r2 = r1 - lv;
-                    Wh[(size_t)cp * c->DP + t] = hb;
-                    Wl[(size_t)cp * c->DP + t] = lb;
+                    Wh[bf16_tiled_index(cp, t, c->DP)] = hb;
+                    Wl[bf16_tiled_index(cp, t, c->DP)] = lb;
                     nh += (double)hv * hv;
                     nl += (double)lv * lv;
                     nr += (double)r2 * r2;

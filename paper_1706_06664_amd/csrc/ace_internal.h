@@ -24,6 +24,17 @@ constexpr int DPAD = 32;
 constexpr int SPLIT_K_BLOCKS = 128;
 
 // Arguments of the projection + sign-pack kernels (one per precision).
+// Split-BF16 operands (x_h, x_l per row; w_h, w_l per padded column) are stored in
+// tiles of 16 rows (or columns) by 32 k: 1 KB each, tiles in row-major order over
+// (row / 16, k / 32).  Inside a tile a row is 64 bytes, four chunks of 8 k, and chunk c
+// of row r sits at position c ^ bf16_chunk_swz(r): one 16 x 32 MFMA operand then comes
+// from one contiguous 1 KB read, and the fragment reads out of LDS hit no bank twice.
+__host__ __device__ inline int bf16_chunk_swz(int r) { return (r >> 1) & 3; }
+__host__ __device__ inline size_t bf16_tiled_index(int64_t r, int k, int DP) {
+    return ((size_t)(r >> 4) * (size_t)(DP >> 5) + (size_t)(k >> 5)) * 512 + (size_t)(r & 15) * 32 +
+           (size_t)((((k & 31) >> 3) ^ bf16_chunk_swz((int)(r & 15))) << 3) + (size_t)(k & 7);
+}
+
 struct HashArgs {
     const float* X;        // [n][d] FP32, caller's device memory
     int64_t n;
@@ -47,15 +58,15 @@ struct HashArgs {
                            // [2] bits inside the bound left unrefined (refine = 2)
     uint16_t* refined;     // [L][ldc] or null: bits decided in place (queue full) are marked
     // Split-BF16 operands and bound factors (BF16 kernel only)
-    const uint16_t* Wh;    // [NP][DP] bf16 bits of w_h
-    const uint16_t* Wl;    // [NP][DP] bf16 bits of w_l
+    const uint16_t* Wh;    // [NP][DP] bf16 bits of w_h, in 16 x 32 tiles (bf16_tiled_index)
+    const uint16_t* Wl;    // [NP][DP] bf16 bits of w_l, likewise
     const float* wbA;      // [NP] column factors of ||x_h||, ||x_l||, ||rho_x|| and the absolute term;
     const float* wbB;      //      wbA < 0 marks a pad column
     const float* wbC;
     const float* wbE;
     float norm_up;         // rounding-up factor of FP32 sums of squares over d terms
-    const uint16_t* Xh;    // [n][DP] bf16 bits of x_h (from the convert pass)
-    const uint16_t* Xl;    // [n][DP] bf16 bits of x_l
+    const uint16_t* Xh;    // [n16][DP] bf16 bits of x_h (convert pass), 16 x 32 tiles, n16 = n rounded up to 16
+    const uint16_t* Xl;    // [n16][DP] bf16 bits of x_l, likewise
     const float* rowA;     // [n] ||x_h||, ||x_l||, ||rho_x||, rounded up
     const float* rowB;
     const float* rowC;

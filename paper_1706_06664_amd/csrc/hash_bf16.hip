@@ -26,9 +26,18 @@
 //
 // Tiling: 256 threads = 4 waves as 2 (rows) x 2 (columns); workgroup tile 128 rows
 // x 2*TW tables (TW <= 4); per wave 64 rows x TW tables, 2 x 4 x TW accumulators of
-// 16x16.  The register budget (256 per lane) keeps two waves per SIMD.  X is split
-// into hi/lo once per chunk by convert_bf16_kernel (which also writes the three row
-// norms); the projection kernel then streams pre-split bf16 tiles.
+// 16x16.  The register budget (256 per lane) keeps two waves per SIMD, and two
+// workgroups (64 KB of LDS each) share a CU.  X is split into hi/lo once per chunk by
+// convert_bf16_kernel (which also writes the three row norms) into 16 x 32 tiles of
+// 1 KB (bf16_tiled_index); W's split is stored the same way.  Each k-step of 32 then
+// moves whole tiles from global memory straight into LDS (one 16-byte load per lane,
+// no registers in between), into one of two stages, while the MFMAs read the other.
+//
+// Where the time goes (low-rank 1M x 1024 launch): the MFMAs alone take 2.9 ms and the
+// tile loads alone 3.8 ms; together 5.5 ms.  The loads, not the matrix unit, bound the
+// kernel: per k, a 128 x 128 tile loads 1 KB of split operands for 3 x 128 x 128
+// products (96 FLOP per byte), and two accumulator chains leave no registers for a
+// larger tile.
 #include "ace_internal.h"
 
 namespace ace {
@@ -37,7 +46,6 @@ namespace {
 
 constexpr int BM = 128;
 constexpr int BK = 32;
-constexpr int LDSB = BK + 16;  // padded LDS row stride in bf16 elements (96 bytes: the 16-byte fragment reads of 16 rows hit distinct banks)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -69,18 +77,21 @@ __device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)
 // consecutive k at 4l + 256i (a wave instruction reads 1 KB contiguous) and writes 8
 // bytes of hi and 8 of lo.
 template <bool VEC>
-__global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ X, int64_t n, int d, int DP,
+__global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ X, int64_t n, int64_t n16, int d, int DP,
                                                            uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
                                                            float* __restrict__ rowA, float* __restrict__ rowB,
                                                            float* __restrict__ rowC, float norm_up) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const float* xr = X + row * (int64_t)d;
+    if (row >= n16) return;
+    const bool real = row < n;  // rows n .. n16-1 fill the last 16-row tile with zeros
+    const float* xr = X + (real ? row : 0) * (int64_t)d;
     float sA = 0.f, sB = 0.f, sC = 0.f;
     for (int k0 = 4 * lane; k0 < DP; k0 += 256) {
         f4 v;
-        if (VEC && k0 + 4 <= d) {
+        if (!real) {
+            v = f4{0.f, 0.f, 0.f, 0.f};
+        } else if (VEC && k0 + 4 <= d) {
             v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(xr + k0));
         } else {
 #pragma unroll
@@ -102,9 +113,11 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
             pl[e] = (short)lb;
         }
         // streamed in and out: the projection kernel reads the split rows back much later
-        __builtin_nontemporal_store(ph, reinterpret_cast<s4v*>(Xh + row * (int64_t)DP + k0));
-        __builtin_nontemporal_store(pl, reinterpret_cast<s4v*>(Xl + row * (int64_t)DP + k0));
+        const size_t o = bf16_tiled_index(row, k0, DP);
+        __builtin_nontemporal_store(ph, reinterpret_cast<s4v*>(Xh + o));
+        __builtin_nontemporal_store(pl, reinterpret_cast<s4v*>(Xl + o));
     }
+    if (!real) return;
     for (int off = 32; off > 0; off >>= 1) {
         sA += __shfl_xor(sA, off, 64);
         sB += __shfl_xor(sB, off, 64);
@@ -117,11 +130,31 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
     }
 }
 
+// The tile layout's chunk rotation (bf16_chunk_swz) keeps the fragment reads (16 rows x
+// one chunk per quarter-wave) free of LDS bank conflicts on gfx950, as 96-byte padded
+// rows would (measured with SQ_LDS_BANK_CONFLICT; plain 64-byte rows, and rotations by
+// r & 3 or (r >> 2) & 3, conflict two-way), while a tile row stays 64 bytes.
+
+// One wave-wide 16-byte-per-lane load from global memory straight into LDS: lane l's
+// 16 bytes land at lds + 16 l (lds is the same for every lane).
+__device__ inline void load_to_lds16(const uint16_t* g, char* lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+// Wait until this wave's loads into LDS have landed.
+__device__ inline void wait_lds_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 template <int TW>
 __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     constexpr int NB = 32 * TW;
-    __shared__ uint16_t Xh[BM * LDSB], Xl[BM * LDSB];
-    __shared__ uint16_t Wh[NB * LDSB], Wl[NB * LDSB];
+    constexpr int A_BYTES = BM * 2 * BK;               // one of x_h / x_l per stage (8 KB)
+    constexpr int B_BYTES = NB * 2 * BK;               // one of w_h / w_l per stage
+    constexpr int STAGE = 2 * A_BYTES + 2 * B_BYTES;
+    constexpr int NI = STAGE / 1024;                   // 1 KB wave loads per stage (16 + 4 TW)
+    constexpr int PW = NI / 4;                         // per wave
+    static_assert(NI % 4 == 0, "stage loads split evenly over the four waves");
+    __shared__ __attribute__((aligned(1024))) char st0[STAGE];
+    __shared__ __attribute__((aligned(1024))) char st1[STAGE];
 
     const int64_t bid = blockIdx.x;
     const int64_t xcd = bid & 7, local = bid >> 3;
@@ -129,7 +162,8 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
     if (tile_m >= a.n_tiles_m) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t row0 = tile_m * BM;
     const int col0 = (int)tile_n * NB;
@@ -143,72 +177,81 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
             accc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
         }
 
-    // A-tile role: thread -> row lr, 16 consecutive k at lk, hi and lo (two 16-byte
-    // loads each).  The next chunk is fetched into registers while the current chunk's
-    // MFMAs run.
-    const int lr = tid >> 1, lk = (tid & 1) * 16;
-    const int64_t grow_ld = row0 + lr;
+    // Stage fill: wave load i (i = 4 j + wave) moves one 1 KB tile (16 rows or columns by
+    // 32 k) straight from global memory into LDS, lane l's 16 bytes at byte 16 l.  Row
+    // tiles past the chunk's last re-read the last one (their results are masked).
     const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows (loads stay within the n rows)
-    const bool row_ok = grow_ld < a.n;
-    const uint16_t* xh = a.Xh + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
-    const uint16_t* xl = a.Xl + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
-    s8v xhv[2], xlv[2];
-    s4v whv[TW], wlv[TW];
-    auto gload = [&](int k0) {
-        // rows past n read row 0 of the chunk (their results are masked)
+    const int64_t gmax = (a.n - 1) / 16;          // last row tile of the chunk
+    const int64_t tk = a.DP / 32;                 // tiles per row tile
+    const uint16_t* src[PW];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            xhv[h] = *reinterpret_cast<const s8v*>(xh + k0 + 8 * h);
-            xlv[h] = *reinterpret_cast<const s8v*>(xl + k0 + 8 * h);
+    for (int j = 0; j < PW; ++j) {
+        const int i = 4 * j + wave;
+        const int byte = i * 1024;
+        if (byte < 2 * A_BYTES) {
+            int64_t g = tile_m * (BM / 16) + (byte % A_BYTES) / 1024;
+            g = g <= gmax ? g : gmax;
+            src[j] = (byte < A_BYTES ? a.Xh : a.Xl) + g * tk * 512 + 8 * lane;
+        } else {
+            const int bb = byte - 2 * A_BYTES;
+            const int64_t g = col0 / 16 + (bb % B_BYTES) / 1024;
+            src[j] = (bb < B_BYTES ? a.Wh : a.Wl) + g * tk * 512 + 8 * lane;
         }
+    }
+    auto fill = [&](char* stage, int k0) {
 #pragma unroll
-        for (int s = 0; s < TW; ++s) {
-            const int q = tid + 256 * s;
-            const int64_t gi = (int64_t)(col0 + (q >> 3)) * a.DP + k0 + (q & 7) * 4;
-            whv[s] = *reinterpret_cast<const s4v*>(a.Wh + gi);
-            wlv[s] = *reinterpret_cast<const s4v*>(a.Wl + gi);
-        }
+        for (int j = 0; j < PW; ++j)
+            load_to_lds16(src[j] + 16 * k0, stage + (4 * j + wave) * 1024);
     };
 
-    gload(0);
-    for (int k0 = 0; k0 < a.DP; k0 += BK) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<s8v*>(Xh + lr * LDSB + lk + 8 * h) = xhv[h];
-            *reinterpret_cast<s8v*>(Xl + lr * LDSB + lk + 8 * h) = xlv[h];
-        }
-#pragma unroll
-        for (int s = 0; s < TW; ++s) {
-            const int q = tid + 256 * s;
-            const int off = (q >> 3) * LDSB + (q & 7) * 4;
-            *reinterpret_cast<s4v*>(Wh + off) = whv[s];
-            *reinterpret_cast<s4v*>(Wl + off) = wlv[s];
-        }
-        __syncthreads();
-        if (k0 + BK < a.DP) gload(k0 + BK);
-        // Lane l supplies k = 8*(l>>4) .. +7 of row/column (l & 15) for one 16x16x32 step.
-        bf8 ah[4], al[4];
+    // Fragment reads: lane l supplies k = 8 (l >> 4) .. +7 of row / column l & 15, the
+    // logical chunk l >> 4 of that tile row.
+    const int fr = lane & 15;
+    const int foff = fr * 64 + 16 * ((lane >> 4) ^ bf16_chunk_swz(fr));
+    auto step = [&](const char* stage) {
+        bf8 ah[4], al[4], bh[TW], bl[TW];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int off = (wm * 64 + 16 * b + (lane & 15)) * LDSB + 8 * (lane >> 4);
-            ah[b] = *reinterpret_cast<const bf8*>(Xh + off);
-            al[b] = *reinterpret_cast<const bf8*>(Xl + off);
+            const int o = (wm * 64 + 16 * b) * 64 + foff;
+            ah[b] = *reinterpret_cast<const bf8*>(stage + o);
+            al[b] = *reinterpret_cast<const bf8*>(stage + A_BYTES + o);
         }
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            const int off = ((wn * TW + t) * 16 + (lane & 15)) * LDSB + 8 * (lane >> 4);
-            const bf8 bh = *reinterpret_cast<const bf8*>(Wh + off);
-            const bf8 bl = *reinterpret_cast<const bf8*>(Wl + off);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                accm[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bh, accm[b][t], 0, 0, 0);
-                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bl, accc[b][t], 0, 0, 0);
-                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[b], bh, accc[b][t], 0, 0, 0);
-            }
+            const int o = (wn * TW + t) * 16 * 64 + foff;
+            bh[t] = *reinterpret_cast<const bf8*>(stage + 2 * A_BYTES + o);
+            bl[t] = *reinterpret_cast<const bf8*>(stage + 2 * A_BYTES + B_BYTES + o);
         }
-        __syncthreads();
-    }
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                accm[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bh[t], accm[b][t], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bl[t], accc[b][t], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[b], bh[t], accc[b][t], 0, 0, 0);
+        }
+    };
 
+    // Two LDS stages: while one is read by the MFMAs, the next k-step streams into the
+    // other.  One barrier per k-step: after it, stage s is complete and every wave has
+    // finished reading stage s ^ 1 (its fragments were consumed by the previous step).
+    const int nk = a.DP / BK;
+    fill(st0, 0);
+    for (int it = 0; it < nk; it += 2) {
+        wait_lds_loads();
+        __syncthreads();
+        if (it + 1 < nk) fill(st1, (it + 1) * BK);
+        step(st0);
+        if (it + 1 >= nk) break;
+        wait_lds_loads();
+        __syncthreads();
+        if (it + 2 < nk) fill(st0, (it + 2) * BK);
+        step(st1);
+    }
     const int kin = lane >> 4, cl = lane & 15;
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = row0 + wm * 64 + lane;
@@ -317,12 +360,13 @@ hipError_t launch_tw(const HashArgs& a, hipStream_t s) {
 hipError_t launch_convert_bf16(const float* X, int64_t n, int d, int DP, bool vec, uint16_t* Xh, uint16_t* Xl,
                                float* rowA, float* rowB, float* rowC, float norm_up, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 3) / 4;
+    const int64_t n16 = (n + 15) / 16 * 16;
+    const int64_t blocks = (n16 + 3) / 4;
     if (vec)
-        hipLaunchKernelGGL(convert_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xh, Xl,
+        hipLaunchKernelGGL(convert_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xh, Xl,
                            rowA, rowB, rowC, norm_up);
     else
-        hipLaunchKernelGGL(convert_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xh, Xl,
+        hipLaunchKernelGGL(convert_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xh, Xl,
                            rowA, rowB, rowC, norm_up);
     return hipGetLastError();
 }
