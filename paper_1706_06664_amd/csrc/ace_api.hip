@@ -57,7 +57,8 @@ ace_status ws_alloc(ace_ctx c, Workspace* w, int64_t rows) {
         st = st ? st : dev_alloc(c, (void**)&w->xh, sizeof(uint16_t) * rows16 * c->DP);
         st = st ? st : dev_alloc(c, (void**)&w->xl, sizeof(uint16_t) * rows16 * c->DP);
     }
-    if (c->cfg.precision == ACE_FP8E4M3) st = st ? st : dev_alloc(c, (void**)&w->xq, (size_t)rows * c->DP);
+    if (c->cfg.precision == ACE_FP8E4M3)
+        st = st ? st : dev_alloc(c, (void**)&w->xq, (size_t)(rows + 15) / 16 * 16 * c->DP);
     if (c->cfg.precision != ACE_FP32) st = st ? st : dev_alloc(c, (void**)&w->rown, sizeof(float) * 3 * (size_t)rows);
     if (st) ws_free(w);
     return st;
@@ -583,7 +584,7 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
                 for (int t = 0; t < d; ++t) {
                     const float w = ldexpf(W_host[(size_t)t * K * L + (size_t)j * K + k], -ex);
                     float q;
-                    Wq[(size_t)cp * c->DP + t] = host_e4m3(w, &q);
+                    Wq[fp8_tiled_index(cp, t, c->DP)] = host_e4m3(w, &q);
                     nq += (double)q * q;
                     nd += (double)(w - q) * (w - q);
                 }

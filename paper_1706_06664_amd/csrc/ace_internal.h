@@ -24,15 +24,23 @@ constexpr int DPAD = 32;
 constexpr int SPLIT_K_BLOCKS = 128;
 
 // Arguments of the projection + sign-pack kernels (one per precision).
-// Split-BF16 operands (x_h, x_l per row; w_h, w_l per padded column) are stored in
-// tiles of 16 rows (or columns) by 32 k: 1 KB each, tiles in row-major order over
-// (row / 16, k / 32).  Inside a tile a row is 64 bytes, four chunks of 8 k, and chunk c
-// of row r sits at position c ^ bf16_chunk_swz(r): one 16 x 32 MFMA operand then comes
-// from one contiguous 1 KB read, and the fragment reads out of LDS hit no bank twice.
-__host__ __device__ inline int bf16_chunk_swz(int r) { return (r >> 1) & 3; }
+// Low-precision operands (split-BF16 x_h, x_l, w_h, w_l; e4m3 x^, w^) are stored in
+// tiles of 16 rows (or padded columns) so that one 16-row MFMA operand block of a k-step
+// is one contiguous read.  Inside a tile a row has 64-byte segments of four 16-byte
+// chunks, and chunk c of row r sits at position c ^ tile_chunk_swz(r): fragment reads of
+// 16 rows x one chunk out of LDS then hit no bank twice on gfx950.
+//   BF16: 16 rows x 32 k (1 KB) per tile, tiles row-major over (row / 16, k / 32).
+//   e4m3: 16 rows x 128 k (2 KB) per tile, over (row / 16, k / 128); bytes 64 h .. 64 h + 63
+//         of each row form sub-tile h (1 KB).
+__host__ __device__ inline int tile_chunk_swz(int r) { return (r >> 1) & 3; }
 __host__ __device__ inline size_t bf16_tiled_index(int64_t r, int k, int DP) {
     return ((size_t)(r >> 4) * (size_t)(DP >> 5) + (size_t)(k >> 5)) * 512 + (size_t)(r & 15) * 32 +
-           (size_t)((((k & 31) >> 3) ^ bf16_chunk_swz((int)(r & 15))) << 3) + (size_t)(k & 7);
+           (size_t)((((k & 31) >> 3) ^ tile_chunk_swz((int)(r & 15))) << 3) + (size_t)(k & 7);
+}
+__host__ __device__ inline size_t fp8_tiled_index(int64_t r, int k, int DP) {
+    return ((size_t)(r >> 4) * (size_t)(DP >> 7) + (size_t)(k >> 7)) * 2048 + (size_t)((k >> 6) & 1) * 1024 +
+           (size_t)(r & 15) * 64 + (size_t)((((k & 63) >> 4) ^ tile_chunk_swz((int)(r & 15))) << 4) +
+           (size_t)(k & 15);
 }
 
 struct HashArgs {
@@ -70,8 +78,8 @@ struct HashArgs {
     const float* rowA;     // [n] ||x_h||, ||x_l||, ||rho_x||, rounded up
     const float* rowB;
     const float* rowC;
-    const uint8_t* Xq;     // [n][DP] e4m3 codes of the scaled rows (FP8 kernel)
-    const uint8_t* Wq;     // [NP][DP] e4m3 codes of the scaled columns
+    const uint8_t* Xq;     // [n16][DP] e4m3 codes of the scaled rows (FP8 kernel), 16 x 128 tiles
+    const uint8_t* Wq;     // [NP][DP] e4m3 codes of the scaled columns, likewise
     // Structured projection (hash_struct kernel): the bound is gx * ||x|| + eps_abs
     const uint32_t* sgn;   // [nblk][3][dp / 32] sign bits of D1, D2, D3 (1 = negate)
     const u64* sgn_lane;   // [nblk][3][64]: bit r of word lane = sign bit of element 64 r + lane

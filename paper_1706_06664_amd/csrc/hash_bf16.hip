@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
     }
 }
 
-// The tile layout's chunk rotation (bf16_chunk_swz) keeps the fragment reads (16 rows x
+// The tile layout's chunk rotation (tile_chunk_swz) keeps the fragment reads (16 rows x
 // one chunk per quarter-wave) free of LDS bank conflicts on gfx950, as 96-byte padded
 // rows would (measured with SQ_LDS_BANK_CONFLICT; plain 64-byte rows, and rotations by
 // r & 3 or (r >> 2) & 3, conflict two-way), while a tile row stays 64 bytes.
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     // Fragment reads: lane l supplies k = 8 (l >> 4) .. +7 of row / column l & 15, the
     // logical chunk l >> 4 of that tile row.
     const int fr = lane & 15;
-    const int foff = fr * 64 + 16 * ((lane >> 4) ^ bf16_chunk_swz(fr));
+    const int foff = fr * 64 + 16 * ((lane >> 4) ^ tile_chunk_swz(fr));
     auto step = [&](const char* stage) {
         bf8 ah[4], al[4], bh[TW], bl[TW];
 #pragma unroll

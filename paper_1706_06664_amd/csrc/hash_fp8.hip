@@ -18,8 +18,10 @@
 // the FP64 pass (refine = 1) or only counted (refine = 2).
 //
 // Tiling as in the BF16 kernel: 256 threads = 2 x 2 waves, 128 rows x 2*TW tables per
-// workgroup, k-steps of 128 (one MFMA); each lane supplies 32 consecutive k of one row
-// or column.
+// workgroup, k-steps of 128 (one MFMA).  Rows and columns are stored in 16 x 128 tiles
+// (fp8_tiled_index); each k-step moves whole tiles from global memory straight into one
+// of two LDS stages while the MFMAs read the other.  Lane l supplies the 16 k of chunk
+// l / 16 from both 64-byte halves of its row or column (the same k for both operands).
 #include "ace_internal.h"
 
 namespace ace {
@@ -27,8 +29,7 @@ namespace ace {
 namespace {
 
 constexpr int BM = 128;
-constexpr int BKB = 128;            // k per step (bytes per row of the tile)
-constexpr int LDSR = BKB + 16;      // padded LDS row stride in bytes
+constexpr int BKB = 128;            // k per step (bytes per row of a tile)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
@@ -78,12 +79,16 @@ __device__ inline f4 load4(const float* xr, int k, int d, bool vec) {
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restrict__ X, int64_t n, int d, int DP,
+__global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restrict__ X, int64_t n, int64_t n16, int d, int DP,
                                                           uint8_t* __restrict__ Xq, float* __restrict__ rowA,
                                                           float* __restrict__ rowB, float norm_up) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n) return;
+    if (row >= n16) return;
+    if (row >= n) {  // rows n .. n16-1 fill the last 16-row tile with zeros
+        for (int k = 4 * lane; k < DP; k += 256) *reinterpret_cast<uint32_t*>(Xq + fp8_tiled_index(row, k, DP)) = 0u;
+        return;
+    }
     const float* xr = X + row * (int64_t)d;
     f4 cache[RCACHE];
     float mx = 0.f;
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restric
             word |= code << (8 * b);
         }
         // streamed out: the projection kernel reads the rows back much later
-        __builtin_nontemporal_store(word, reinterpret_cast<uint32_t*>(Xq + row * (int64_t)DP + k));
+        __builtin_nontemporal_store(word, reinterpret_cast<uint32_t*>(Xq + fp8_tiled_index(row, k, DP)));
     };
 #pragma unroll
     for (int i = 0; i < RCACHE; ++i)
@@ -138,11 +143,26 @@ __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restric
     }
 }
 
+// One wave-wide 16-byte-per-lane load from global memory straight into LDS: lane l's
+// 16 bytes land at lds + 16 l (lds is the same for every lane).
+__device__ inline void load_to_lds16(const uint8_t* g, uint8_t* lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+// Wait until this wave's loads into LDS have landed.
+__device__ inline void wait_lds_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 template <int TW>
 __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     constexpr int NB = 32 * TW;
-    __shared__ __attribute__((aligned(16))) uint8_t Xs[BM * LDSR];
-    __shared__ __attribute__((aligned(16))) uint8_t Ws[NB * LDSR];
+    constexpr int A_BYTES = BM * BKB;                  // rows of one k-step (16 KB)
+    constexpr int B_BYTES = NB * BKB;                  // columns of one k-step
+    constexpr int STAGE = A_BYTES + B_BYTES;
+    constexpr int NI = STAGE / 1024;                   // 1 KB wave loads per stage (16 + 4 TW)
+    constexpr int PW = NI / 4;                         // per wave
+    static_assert(NI % 4 == 0, "stage loads split evenly over the four waves");
+    __shared__ __attribute__((aligned(1024))) uint8_t st0[STAGE];
+    __shared__ __attribute__((aligned(1024))) uint8_t st1[STAGE];
 
     const int64_t bid = blockIdx.x;
     const int64_t xcd = bid & 7, local = bid >> 3;
@@ -150,7 +170,8 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
     if (tile_m >= a.n_tiles_m) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t row0 = tile_m * BM;
     const int col0 = (int)tile_n * NB;
@@ -161,62 +182,67 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
 #pragma unroll
         for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // X tile: 128 rows x 128 bytes; thread -> row tid/2, 64 bytes at (tid&1)*64.
-    // W tile: NB columns x 128 bytes as 16-byte quads, TW/2 per thread (TW even) or
-    // spread over the block otherwise.
-    const int lr = tid >> 1, lk = (tid & 1) * 64;
-    const int64_t grow_ld = row0 + lr;
+    // Stage fill: wave load i (i = 4 j + wave) moves one 1 KB sub-tile (16 rows or columns,
+    // one 64-byte half of the k-step) straight into LDS, lane l's 16 bytes at byte 16 l.
+    // Row tiles past the chunk's last re-read the last one (their results are masked).
     const int64_t nv = a.n_dev ? *a.n_dev : a.n;   // real rows (loads stay within the n rows)
-    const bool row_ok = grow_ld < a.n;
-    const uint8_t* xq = a.Xq + (row_ok ? grow_ld : 0) * (int64_t)a.DP + lk;
-    constexpr int WQ = NB * (BKB / 16);          // 16-byte quads in the W tile
-    constexpr int WPT = (WQ + 255) / 256;        // per thread
-    i4v xv[4];
-    i4v wv[WPT];
-    auto gload = [&](int k0) {
+    const int64_t gmax = (a.n - 1) / 16;          // last row tile of the chunk
+    const int64_t tk = a.DP / BKB;                // tiles per row tile
+    const uint8_t* src[PW];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            xv[q] = row_ok ? *reinterpret_cast<const i4v*>(xq + k0 + 16 * q) : i4v{0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < WPT; ++s) {
-            const int q = tid + 256 * s;
-            if (q < WQ) {
-                const int col = q >> 3, kq = (q & 7) * 16;
-                wv[s] = *reinterpret_cast<const i4v*>(a.Wq + (int64_t)(col0 + col) * a.DP + k0 + kq);
-            }
+    for (int j = 0; j < PW; ++j) {
+        const int i = 4 * j + wave;
+        if (i < A_BYTES / 1024) {
+            int64_t g = tile_m * (BM / 16) + i / 2;
+            g = g <= gmax ? g : gmax;
+            src[j] = a.Xq + g * tk * 2048 + (i & 1) * 1024 + 16 * lane;
+        } else {
+            const int ib = i - A_BYTES / 1024;
+            const int64_t g = col0 / 16 + ib / 2;
+            src[j] = a.Wq + g * tk * 2048 + (ib & 1) * 1024 + 16 * lane;
         }
+    }
+    auto fill = [&](uint8_t* stage, int k0) {
+#pragma unroll
+        for (int j = 0; j < PW; ++j) load_to_lds16(src[j] + 16 * k0, stage + (4 * j + wave) * 1024);
     };
 
-    gload(0);
-    for (int k0 = 0; k0 < a.DP; k0 += BKB) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<i4v*>(Xs + lr * LDSR + lk + 16 * q) = xv[q];
-#pragma unroll
-        for (int s = 0; s < WPT; ++s) {
-            const int q = tid + 256 * s;
-            if (q < WQ) *reinterpret_cast<i4v*>(Ws + (q >> 3) * LDSR + (q & 7) * 16) = wv[s];
-        }
-        __syncthreads();
-        if (k0 + BKB < a.DP) gload(k0 + BKB);
-        // Lane l supplies 32 consecutive k (bytes 32*(l>>4) ..) of row/column (l & 15).
+    // Fragment reads: lane l takes chunk l / 16 of row / column l & 15 from both halves.
+    const int fr = lane & 15;
+    const int foff = fr * 64 + 16 * ((lane >> 4) ^ tile_chunk_swz(fr));
+    auto frag = [&](const uint8_t* p) {
+        const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 1024);
+        return i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    };
+    auto step = [&](const uint8_t* stage) {
         i8v af[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint8_t* p = Xs + (wm * 64 + 16 * b + (lane & 15)) * LDSR + 32 * (lane >> 4);
-            const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 16);
-            af[b] = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-        }
+        for (int b = 0; b < 4; ++b) af[b] = frag(stage + (wm * 4 + b) * 2048 + foff);
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            const uint8_t* p = Ws + ((wn * TW + t) * 16 + (lane & 15)) * LDSR + 32 * (lane >> 4);
-            const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 16);
-            const i8v bf = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            const i8v bf = frag(stage + A_BYTES + (wn * TW + t) * 2048 + foff);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 acc[b][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[b], bf, acc[b][t], 0, 0, 0, 127, 0,
                                                                              127);
         }
+    };
+
+    // Two LDS stages: while one is read by the MFMAs, the next k-step streams into the
+    // other.  One barrier per k-step: after it, stage s is complete and every wave has
+    // finished reading stage s ^ 1 (its fragments were consumed by the previous step).
+    const int nk = a.DP / BKB;
+    fill(st0, 0);
+    for (int it = 0; it < nk; it += 2) {
+        wait_lds_loads();
         __syncthreads();
+        if (it + 1 < nk) fill(st1, (it + 1) * BKB);
+        step(st0);
+        if (it + 1 >= nk) break;
+        wait_lds_loads();
+        __syncthreads();
+        if (it + 2 < nk) fill(st0, (it + 2) * BKB);
+        step(st1);
     }
 
     const int kin = lane >> 4, cl = lane & 15;
@@ -316,12 +342,13 @@ hipError_t launch_tw(const HashArgs& a, hipStream_t s) {
 hipError_t launch_convert_fp8(const float* X, int64_t n, int d, int DP, bool vec, uint8_t* Xq, float* rowA,
                               float* rowB, float norm_up, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 3) / 4;
+    const int64_t n16 = (n + 15) / 16 * 16;
+    const int64_t blocks = (n16 + 3) / 4;
     if (vec)
-        hipLaunchKernelGGL(convert_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xq, rowA,
+        hipLaunchKernelGGL(convert_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xq, rowA,
                            rowB, norm_up);
     else
-        hipLaunchKernelGGL(convert_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, DP, Xq, rowA,
+        hipLaunchKernelGGL(convert_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xq, rowA,
                            rowB, norm_up);
     return hipGetLastError();
 }
