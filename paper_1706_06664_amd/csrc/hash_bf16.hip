@@ -71,11 +71,11 @@ __device__ inline uint16_t bf16_bits(float x) {
 }
 __device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Convert + row norms: X (FP32 [n][d]) -> Xh, Xl (bf16 bits [n][DP], zero-padded to
-// DP) and the row norms A = ||x_h||, B = ||x_l||, C = ||rho_x|| (FP32 sums of squares
-// rounded up by norm_up, square roots by 2^-20).  One wave per row; lane l takes the 4
-// consecutive k at 4l + 256i (a wave instruction reads 1 KB contiguous) and writes 8
-// bytes of hi and 8 of lo.
+// Convert + row norms: X (FP32 [n][d]) -> Xh, Xl (bf16 bits in 16 x 32 tiles, zero-padded
+// to DP and to whole 16-row tiles) and the row norms A = ||x_h||, B = ||x_l||,
+// C = ||rho_x|| (FP32 sums of squares rounded up by norm_up, square roots by 2^-20).
+// One wave per row; lane l takes the 4 consecutive k at 4l + 256i (a wave instruction
+// reads 1 KB contiguous) and writes 8 bytes of hi and 8 of lo.
 template <bool VEC>
 __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ X, int64_t n, int64_t n16, int d, int DP,
                                                            uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
@@ -112,10 +112,12 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
             ph[e] = (short)hb;
             pl[e] = (short)lb;
         }
-        // streamed in and out: the projection kernel reads the split rows back much later
+        // Plain stores: a row fills half of each 128-byte line of a tile and the next row
+        // (another wave of the block) the other half; the cache merges them (nontemporal
+        // stores of the halves took 15.6 against 13.3 ms per low-rank step).
         const size_t o = bf16_tiled_index(row, k0, DP);
-        __builtin_nontemporal_store(ph, reinterpret_cast<s4v*>(Xh + o));
-        __builtin_nontemporal_store(pl, reinterpret_cast<s4v*>(Xl + o));
+        *reinterpret_cast<s4v*>(Xh + o) = ph;
+        *reinterpret_cast<s4v*>(Xl + o) = pl;
     }
     if (!real) return;
     for (int off = 32; off > 0; off >>= 1) {
