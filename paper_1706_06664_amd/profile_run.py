@@ -18,6 +18,7 @@ def main():
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--rows", type=int, default=1_000_000)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--refine", type=int, default=1, help="0 raw signs, 1 FP64 pass (default), 2 count only")
     args = ap.parse_args()
     import torch
     from ace_inputs import c2_points, heavy_tail_points_torch, low_rank_points_torch, projection_matrix
@@ -32,7 +33,7 @@ def main():
     else:
         Xd, _ = heavy_tail_points_torch(args.rows, 4096, seed=4, device="cuda")
         W, K, L = projection_matrix(4096, 16, 100, 1706066644), 16, 100
-    ace = ACE(W, K, L, precision=args.precision)
+    ace = ACE(W, K, L, precision=args.precision, refine=args.refine)
     for i in range(args.reps):
         ace.hash(Xd)
         torch.cuda.synchronize()
