@@ -81,8 +81,13 @@ __global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
 // entry's row and column with 16-byte loads (eight lanes per entry, so each load
 // instruction reads eight whole 128-byte segments), parks them in LDS, and then every lane
 // runs its entry's FP64 sum over the chunk in ascending t.  The sum and the bit patch are
-// those of refine_kernel; only the memory access pattern differs.  All waves of a block
-// step through the same chunks, so the block-wide barriers match.
+// those of refine_kernel; only the memory access pattern differs.
+// Each wave stages into its own LDS slice, so a wave-level ordering point suffices: LDS
+// operations of one wave complete in issue order.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 constexpr int RC = 32;        // k per chunk
 constexpr int RS = RC + 1;    // LDS row stride in floats (lane e reads row e: distinct banks)
 
@@ -128,12 +133,12 @@ __global__ __launch_bounds__(256, 2) void refine_staged_kernel(const RefineArgs 
                     ww[ee * RS + q + u] = wv[u];
                 }
             }
-            __syncthreads();
+            wave_sync();
             // Past d the staged values are zeros: adding an exact zero leaves the sum's
             // value unchanged (at most -0 becomes +0, which is not > 0 either way).
 #pragma unroll 8
             for (int t = 0; t < RC; ++t) s = fma((double)xw[lane * RS + t], (double)ww[lane * RS + t], s);
-            __syncthreads();
+            wave_sync();
         }
         if (ok) {
             const bool raw = (e >> 63) != 0;
