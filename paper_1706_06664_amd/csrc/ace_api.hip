@@ -186,13 +186,24 @@ uint8_t host_e4m3(float v, float* q) {
 }
 
 int pick_tw(int L, bool fp32) {
-    // Fewest padded tables; ties go to the wider tile.  The split-BF16 kernel holds two
-    // accumulator chains and is built for TW <= 4.
-    const int cand[] = {5, 4, 8, 2, 1};
-    int best = fp32 ? 5 : 4;
+    // The split-BF16 kernel holds two accumulator chains and is built for TW <= 4.  Its
+    // time goes to moving operand tiles, so a wider tile pays for a few padded tables:
+    // take the widest whose padding is at most L / 16 (connection-log L = 50: TW = 2,
+    // 0.54 against 0.63 ms at TW = 1 and 0.56 at TW = 4; heavy-tail L = 100: TW = 4,
+    // 9.39 against 9.70 ms per 250k rows at TW = 2).
+    if (!fp32) {
+        for (int tw : {4, 2}) {
+            const long pad = (long)(L + 2 * tw - 1) / (2 * tw) * (2 * tw) - L;
+            if (16 * pad <= L) return tw;
+        }
+        return 1;
+    }
+    // FP32 and e4m3: fewest padded tables; ties go to the wider tile.  (TW = 8 never wins:
+    // its padding is never below that of TW = 4.)
+    const int cand[] = {5, 4, 2, 1};
+    int best = 5;
     long best_pad = -1;
     for (int tw : cand) {
-        if (!fp32 && tw > 4) continue;
         const long tiles = (L + 2 * tw - 1) / (2 * tw);
         const long pad = tiles * 2 * tw - L;
         if (best_pad < 0 || pad < best_pad) {

@@ -359,7 +359,6 @@ hipError_t launch_hash_fp8(const HashArgs& a, int TW, hipStream_t s) {
         case 2: return launch_tw<2>(a, s);
         case 4: return launch_tw<4>(a, s);
         case 5: return launch_tw<5>(a, s);
-        case 8: return launch_tw<8>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
