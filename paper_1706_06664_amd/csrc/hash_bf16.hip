@@ -49,7 +49,6 @@ constexpr int BK = 32;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef short s8v __attribute__((ext_vector_type(8)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 
 __device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane) {
