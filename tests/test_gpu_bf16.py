@@ -38,6 +38,15 @@ def test_bf16_parity_shapes(n, d, K, L):
     _say((n, d, K, L, r))
 
 
+def test_bf16_tiny_chunks_long_rows():
+    """Chunks of 16 rows (one row tile each, the last chunk a single row) and rows whose
+    padded width is an odd number of 32-wide k-steps (d = 4100: 129 steps)."""
+    X, _ = gaussian_clusters(17, 4100, 2, 0.05, seed=4117)
+    W = projection_matrix(4100, 16, 20, 4118)
+    r = full_parity(X, W, 16, 20, precision="bf16", max_batch_rows=16)
+    _say(r)
+
+
 def test_bf16_connection_log_sample():
     X, _ = c2_points(n=30_000, seed=12)
     W = projection_matrix(120, 15, 50, 1706066642)

@@ -71,6 +71,14 @@ def test_fp8_parity_shapes(n, d, K, L):
     _say((n, d, K, L, r))
 
 
+def test_fp8_tiny_chunks_long_rows():
+    """Chunks of 16 rows (the last a single row) and rows of 33 k-steps of 128 (d = 4100)."""
+    X, _ = gaussian_clusters(17, 4100, 2, 0.05, seed=4127)
+    W = projection_matrix(4100, 16, 20, 4128)
+    r = full_parity(X, W, 16, 20, precision="fp8", max_batch_rows=16)
+    _say(r)
+
+
 @pytest.mark.parametrize("shape", ["connection_log", "heavy_tail_512"])
 def test_fp8_raw_signs_stay_inside_stated_bound(shape):
     import torch
