@@ -106,33 +106,51 @@ __global__ __launch_bounds__(256, 2) void refine_staged_kernel(const RefineArgs 
         const int64_t row = (int64_t)(e & 0xFFFFFFFFull);
         const int cp = (int)((e >> 32) & 0xFFFFu);
         double s = 0.0;
+        // Lane l stages 4 values of entry 8j + l/8 (j = 0..7) at t0 + 4 (l % 8); the next
+        // chunk's loads are issued before the current chunk is summed.
+        const int q = 4 * (lane & 7);
+        const float* xr[8];
+        const float* wr[8];
+        bool eok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int ee = 8 * j + (lane >> 3);
+            const int64_t er = __shfl(row, ee, 64);
+            const int ec = __shfl(cp, ee, 64);
+            eok[j] = g0 + (u64)(64 * wave + ee) < n_ent;
+            xr[j] = a.X + er * (int64_t)d + q;
+            wr[j] = a.Wt + (int64_t)ec * a.DP + q;
+        }
+        f4 xv[8], wv[8];
+        auto load = [&](int t0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                xv[j] = f4{0.f, 0.f, 0.f, 0.f};
+                wv[j] = f4{0.f, 0.f, 0.f, 0.f};
+                if (eok[j]) {
+                    if (t0 + q + 4 <= d) {
+                        xv[j] = *reinterpret_cast<const f4*>(xr[j] + t0);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) xv[j][u] = (t0 + q + u < d) ? xr[j][t0 + u] : 0.f;
+                    }
+                    // W^T rows are zero-padded to DP, a multiple of the chunk size.
+                    wv[j] = *reinterpret_cast<const f4*>(wr[j] + t0);
+                }
+            }
+        };
+        load(0);
         for (int t0 = 0; t0 < d; t0 += RC) {
-            // Lane l stages 4 values of entry 8j + l/8 (j = 0..7) at t0 + 4 (l % 8).
-            const int q = 4 * (lane & 7);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int ee = 8 * j + (lane >> 3);
-                const int64_t er = __shfl(row, ee, 64);
-                const int ec = __shfl(cp, ee, 64);
-                const bool eok = g0 + (u64)(64 * wave + ee) < n_ent;
-                f4 xv = f4{0.f, 0.f, 0.f, 0.f}, wv = f4{0.f, 0.f, 0.f, 0.f};
-                if (eok) {
-                    const float* xr = a.X + er * (int64_t)d + t0 + q;
-                    if (t0 + q + 4 <= d) {
-                        xv = *reinterpret_cast<const f4*>(xr);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) xv[u] = (t0 + q + u < d) ? xr[u] : 0.f;
-                    }
-                    // W^T rows are zero-padded to DP, a multiple of the chunk size.
-                    wv = *reinterpret_cast<const f4*>(a.Wt + (int64_t)ec * a.DP + t0 + q);
-                }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    xw[ee * RS + q + u] = xv[u];
-                    ww[ee * RS + q + u] = wv[u];
+                    xw[ee * RS + q + u] = xv[j][u];
+                    ww[ee * RS + q + u] = wv[j][u];
                 }
             }
+            if (t0 + RC < d) load(t0 + RC);
             wave_sync();
             // Past d the staged values are zeros: adding an exact zero leaves the sum's
             // value unchanged (at most -0 becomes +0, which is not > 0 either way).
