@@ -210,9 +210,10 @@ def test_parity_connection_log_full():
     _say(r)
 
 
-def test_refine_queue_full_path():
-    """With the queue cut to 10 entries nearly every uncertain projection is decided inside
-    the projection kernel; codes and refine counts must match the default path."""
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
+def test_refine_queue_full_path(precision):
+    """With the queue cut to 0 or 10 entries nearly every uncertain projection is decided
+    inside the projection kernel; codes, refine counts and refined masks must match."""
     import torch
     from paper_1706_06664_amd import ACE, codes_as_uint16
     rng = np.random.default_rng(6)
@@ -230,7 +231,7 @@ def test_refine_queue_full_path():
     co, amb = oracle.hash_codes(X, W, K, L)
     res = []
     for q in (0, 10):
-        ace = ACE(W, K, L)
+        ace = ACE(W, K, L, precision=precision)
         assert ace.lib.ace_debug_set_refine_queue(ace.h, q) == 0
         cg, ref = ace.hash(Xd, want_refined=True)
         cg = codes_as_uint16(cg)
