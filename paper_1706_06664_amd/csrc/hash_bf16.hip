@@ -159,8 +159,11 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
 
     const int64_t bid = blockIdx.x;
     const int64_t xcd = bid & 7, local = bid >> 3;
-    const int64_t tile_n = local % a.n_tiles_n;
-    const int64_t tile_m = (local / a.n_tiles_n) * 8 + xcd;
+    // Per XCD, groups of 8 row tiles: one column tile after another, each across the
+    // group's 8 row tiles (so consecutive workgroups share the column tiles they load).
+    const int64_t grp = local / (8 * a.n_tiles_n), rr = local % (8 * a.n_tiles_n);
+    const int64_t tile_n = rr / 8;
+    const int64_t tile_m = (grp * 8 + rr % 8) * 8 + xcd;
     if (tile_m >= a.n_tiles_m) return;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -350,8 +353,8 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
 
 template <int TW>
 hipError_t launch_tw(const HashArgs& a, hipStream_t s) {
-    const int64_t groups = (a.n_tiles_m + 7) / 8;
-    const int64_t blocks = groups * 8 * a.n_tiles_n;
+    const int64_t groups = (a.n_tiles_m + 63) / 64;
+    const int64_t blocks = groups * 64 * a.n_tiles_n;
     hipLaunchKernelGGL((hash_bf16_kernel<TW>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
