@@ -73,20 +73,22 @@ __device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)
 // Convert + row norms: X (FP32 [n][d]) -> Xh, Xl (bf16 bits in 16 x 32 tiles, zero-padded
 // to DP and to whole 16-row tiles) and the row norms A = ||x_h||, B = ||x_l||,
 // C = ||rho_x|| (FP32 sums of squares rounded up by norm_up, square roots by 2^-20).
-// One wave per row; lane l takes the 4 consecutive k at 4l + 256i (a wave instruction
-// reads 1 KB contiguous) and writes 8 bytes of hi and 8 of lo.
-template <bool VEC>
+// LPR lanes per row (64 for rows of 256 or more k, fewer for short rows, so that no lane
+// idles): lane l of a row takes the 4 consecutive k at 4l + 4 LPR i and writes 8 bytes of
+// hi and 8 of lo.
+template <bool VEC, int LPR>
 __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ X, int64_t n, int64_t n16, int d, int DP,
                                                            uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
                                                            float* __restrict__ rowA, float* __restrict__ rowB,
                                                            float* __restrict__ rowC, float norm_up) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n16) return;
+    constexpr int RPW = 64 / LPR;  // rows per wave
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + (threadIdx.x & 63) / LPR;
+    if (row >= n16) return;        // a row's LPR lanes leave together
     const bool real = row < n;  // rows n .. n16-1 fill the last 16-row tile with zeros
     const float* xr = X + (real ? row : 0) * (int64_t)d;
     float sA = 0.f, sB = 0.f, sC = 0.f;
-    for (int k0 = 4 * lane; k0 < DP; k0 += 256) {
+    for (int k0 = 4 * lane; k0 < DP; k0 += 4 * LPR) {
         f4 v;
         if (!real) {
             v = f4{0.f, 0.f, 0.f, 0.f};
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restri
         *reinterpret_cast<s4v*>(Xl + o) = pl;
     }
     if (!real) return;
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = LPR / 2; off > 0; off >>= 1) {  // within the row's lanes
         sA += __shfl_xor(sA, off, 64);
         sB += __shfl_xor(sB, off, 64);
         sC += __shfl_xor(sC, off, 64);
@@ -365,13 +367,19 @@ hipError_t launch_convert_bf16(const float* X, int64_t n, int d, int DP, bool ve
                                float* rowA, float* rowB, float* rowC, float norm_up, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t n16 = (n + 15) / 16 * 16;
-    const int64_t blocks = (n16 + 3) / 4;
-    if (vec)
-        hipLaunchKernelGGL(convert_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xh, Xl,
-                           rowA, rowB, rowC, norm_up);
-    else
-        hipLaunchKernelGGL(convert_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, Xh, Xl,
-                           rowA, rowB, rowC, norm_up);
+    const int lpr = DP >= 256 ? 64 : DP >= 128 ? 32 : DP >= 64 ? 16 : 8;  // DP is a multiple of 32
+    const int64_t rows_per_block = 4 * (64 / lpr);
+    const int64_t blocks = (n16 + rows_per_block - 1) / rows_per_block;
+#define ACE_CONVERT(V, P)                                                                                     \
+    hipLaunchKernelGGL((convert_bf16_kernel<V, P>), dim3((unsigned)blocks), dim3(256), 0, s, X, n, n16, d, DP, \
+                       Xh, Xl, rowA, rowB, rowC, norm_up)
+    switch (lpr) {
+        case 64: if (vec) ACE_CONVERT(true, 64); else ACE_CONVERT(false, 64); break;
+        case 32: if (vec) ACE_CONVERT(true, 32); else ACE_CONVERT(false, 32); break;
+        case 16: if (vec) ACE_CONVERT(true, 16); else ACE_CONVERT(false, 16); break;
+        default: if (vec) ACE_CONVERT(true, 8); else ACE_CONVERT(false, 8); break;
+    }
+#undef ACE_CONVERT
     return hipGetLastError();
 }
 
