@@ -9,7 +9,7 @@ hundred points at most.
 from __future__ import annotations
 
 from fractions import Fraction
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Sequence
 
 
 def exact_projection(x: Sequence[float], w_col: Sequence[float]) -> Fraction:
@@ -66,10 +66,3 @@ class TinyACE:
     def score(self, codes_row: Sequence[int]) -> Fraction:
         return sum((Fraction(self.tables[j].get(b, 0)) for j, b in enumerate(codes_row)), Fraction(0)) / self.L
 
-
-def population_moments(scores: Sequence[Fraction]) -> Tuple[Fraction, Fraction]:
-    """Mean and population variance of a list of exact scores."""
-    m = len(scores)
-    mean = sum(scores, Fraction(0)) / m
-    var = sum(((s - mean) ** 2 for s in scores), Fraction(0)) / m
-    return mean, var

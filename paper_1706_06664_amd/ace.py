@@ -31,7 +31,7 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
-           "ace_server_destroy", "ace_exact_score", "ace_create_structured"]
+           "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH):
         "ace_server_destroy": [P],
         "ace_exact_score": [P, i64, P, i64, i32, i32, P, P, i32, P],
         "ace_create_structured": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
+        "ace_mfma_probe": [i32, P, P, P, P, i32],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -340,6 +341,26 @@ def exact_score(Q, X, K: int, want_S2: bool = False, stream=None):
                                int(K), S.data_ptr(), S2.data_ptr() if S2 is not None else None,
                                Q.device.index or 0, _stream_ptr(stream)), "ace_exact_score")
     return (S, S2) if want_S2 else S
+
+
+_PROBE = {"fp32": (0, np.float32, (16, 4), (4, 16)), "bf16": (1, np.uint16, (16, 32), (32, 16)),
+          "e4m3": (2, np.uint8, (16, 128), (128, 16))}
+
+
+def mfma_probe(kind: str, A: np.ndarray, B: np.ndarray, C: np.ndarray, device: int = 0) -> np.ndarray:
+    """One matrix instruction D = C + A B on the GPU (ace_mfma_probe): kind "fp32" (A, B
+    float32 [16][4], [4][16]), "bf16" (uint16 bf16 bits [16][32], [32][16]) or "e4m3"
+    (uint8 codes [16][128], [128][16]); C float32 [16][16].  Returns D float32 [16][16]."""
+    k, dt, sa, sb = _PROBE[kind]
+    A = np.ascontiguousarray(A, dt)
+    B = np.ascontiguousarray(B, dt)
+    C = np.ascontiguousarray(C, np.float32)
+    if A.shape != sa or B.shape != sb or C.shape != (16, 16):
+        raise ValueError(f"{kind}: A {sa}, B {sb}, C (16, 16) expected")
+    D = np.empty((16, 16), np.float32)
+    _check(load_library().ace_mfma_probe(k, A.ctypes.data, B.ctypes.data, C.ctypes.data, D.ctypes.data, device),
+           "ace_mfma_probe")
+    return D
 
 
 def _host_ptr(a, dtype, what: str):

@@ -426,6 +426,10 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
     if (cfg->refine < 0 || cfg->refine > 2) return ACE_E_INVALID;
     if (cfg->max_batch_rows < 0 || cfg->mem_budget < 0 || cfg->device < 0) return ACE_E_INVALID;
     if (cfg->bound_model != ACE_BOUND_MEASURED && cfg->bound_model != ACE_BOUND_GENERIC) return ACE_E_INVALID;
+    // The generic model charges each addition a rounding of 2^-23 relative to the sum; the
+    // e4m3 instruction is measured to drop bits far above that (about 2^-13 of a k-group's
+    // largest product), so no generic bound is offered for it.
+    if (cfg->precision == ACE_FP8E4M3 && cfg->bound_model == ACE_BOUND_GENERIC) return ACE_E_INVALID;
     if (cfg->counter_bits != 0 && cfg->counter_bits != 16 && cfg->counter_bits != 32) return ACE_E_INVALID;
     if ((int64_t)cfg->d > (int64_t)1 << 24) return ACE_E_INVALID;
 

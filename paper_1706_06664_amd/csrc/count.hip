@@ -306,7 +306,16 @@ __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__
 }
 
 // Threshold statistics from the exact sums (one thread).
-__device__ inline double u128_to_double(u64 lo, u64 hi) { return (double)hi * 0x1p64 + (double)lo; }
+// Unsigned 128-bit integer to the nearest double (ties to even): the top 64 significant
+// bits, with a sticky bit for anything below them, go through the correctly rounded u64
+// conversion (the sticky bit sits below the rounding position), then an exact scaling.
+__device__ inline double u128_to_double(u64 lo, u64 hi) {
+    if (hi == 0) return (double)lo;
+    const int sh = __clzll((long long)hi);             // 0..63
+    const u64 top = sh ? (hi << sh) | (lo >> (64 - sh)) : hi;
+    const u64 rest = lo << sh;                          // bits below the top 64 (sh = 0: all of lo)
+    return ldexp((double)(top | (rest != 0 ? 1ull : 0ull)), 64 - sh);
+}
 
 __global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, const u64* __restrict__ S3,
                                  const u64* __restrict__ mom, int mode, double alpha, DevThresh* __restrict__ out) {
@@ -316,9 +325,11 @@ __global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, c
     r.m_scored = (int64_t)mom[0];
     r.mode = mode;
     r.status = 0;
-    i128 s2tot = 0;
-    for (int j = 0; j < L; ++j) s2tot += (i128)(int64_t)S2[j];
-    r.mu = n > 0 ? (double)(int64_t)s2tot / ((double)n * (double)L) : 0.0;
+    // sum_j S2_j reaches 2^63 well inside the INT32_MAX insert cap (L tables of n^2 each):
+    // it is summed and converted in 128 bits.
+    u128 s2tot = 0;
+    for (int j = 0; j < L; ++j) s2tot += (u128)S2[j];
+    r.mu = n > 0 ? u128_to_double((u64)s2tot, (u64)(s2tot >> 64)) / ((double)n * (double)L) : 0.0;
     const int64_t m = (int64_t)mom[0];
     const int64_t sumT = (int64_t)mom[1];
     r.mu_scored = 0.0;

@@ -112,15 +112,16 @@ __global__ __launch_bounds__(256) void convert_fp8_kernel(const float* __restric
         e = ilogbf(mx / 448.f);
         while (ldexpf(mx, -e) > 448.f) ++e;
     }
-    const float sc = ldexpf(1.f, -e);
+    // The scaling is one exact ldexp per value: 2^-e itself overflows FP32 for rows whose
+    // largest value is below about 2^-119.
     float sA = 0.f, sB = 0.f;
     auto encode = [&](f4 v, int k) {
         uint32_t word = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const float x = v[b] * sc;
+            const float x = ldexpf(v[b], -e);
             float qv;
-            const uint32_t code = e4m3_encode(x, qv);
+            const uint32_t code = e4m3_encode(x, qv) & 0xFFu;
             const float dx = x - qv;  // exact
             sA = fmaf(qv, qv, sA);
             sB = fmaf(dx, dx, sB);

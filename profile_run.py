@@ -1,6 +1,6 @@
 """Small driver for counter runs of one projection kernel (used under rocprofv3).
 
-    python -m paper_1706_06664_amd.profile_run --workload low_rank --precision bf16
+    python3 profile_run.py --workload low_rank --precision bf16
 
 Generates the workload's rows on the device (seeded, as the benchmark does), creates the
 context and hashes the rows `--reps` times.  Prints one line per step."""
@@ -8,7 +8,7 @@ import argparse
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 

@@ -17,6 +17,9 @@ What pins what (arXiv 1706.06664):
   deletion             - insert then delete equals never inserting (Eq. dynsub)
   collision_law        - Monte Carlo SRP collision rate vs 1 - theta/pi (Eq. srp, Eq. metasrp)
   unbiased             - mean over many tables of A_j[H_j(q)] vs sum_i p_i^K (Theorem 1)
+  zero_vectors         - S(q, D) with zero rows: p = 1 for two zero vectors and 1/2 for a
+                         zero and a nonzero one (Eq. srp under the sign(0) -> 0 reading),
+                         against the closed form and a Monte Carlo over the oracle's hash
   table_sigma_bound    - the per-table sigma bounds the inserted points' sigma
   saturating_counters  - short counters (Sec. 3.4) with a cap: stored counts equal
                          min(true count, cap) in any insertion order, S2/S3 follow
@@ -311,6 +314,45 @@ def unbiased(seed: int = 20, L: int = 60_000):
         assert int(T[0]) == int(per_table.sum())
 
 
+def zero_vectors(seed: int = 23, R: int = 200_000):
+    """Eq. thescore with zero vectors.  A zero vector projects to 0 on every column, so under
+    the sign(0) -> 0 reading all its bits are 0: it collides with another zero vector on every
+    bit (p = 1) and with a nonzero vector on half of the bits on average (p = 1/2, the
+    nonzero vector's bit being a fair coin over W ~ N(0, I)).  Checked two ways that do not go
+    through the exact-score routine: the closed form sum of p^K with those p and brute-force
+    angles for the nonzero pairs, and a Monte Carlo of bit collisions over R columns of the
+    oracle's own hash."""
+    rng = np.random.default_rng(seed)
+    d, K = 5, 3
+    X = rng.standard_normal((7, d)).astype(np.float32)
+    X[[1, 4]] = 0.0
+    Q = np.stack([np.zeros(d, np.float32), X[0], rng.standard_normal(d).astype(np.float32)])
+    S = oracle.exact_score(Q, X, K)
+    for a in range(Q.shape[0]):
+        q = Q[a].astype(np.float64)
+        want = 0.0
+        for x in X.astype(np.float64):
+            qz, xz = not q.any(), not x.any()
+            if qz and xz:
+                p = 1.0
+            elif qz or xz:
+                p = 0.5
+            else:
+                cs = float(np.clip(q @ x / (np.linalg.norm(q) * np.linalg.norm(x)), -1, 1))
+                p = 1.0 - math.acos(cs) / math.pi
+            want += p ** K
+        assert abs(S[a] - want) <= 1e-12 * max(1.0, want), (a, S[a], want)
+    # zero query against only zero rows: every pair collides surely, S = n
+    assert oracle.exact_score(Q[:1], X[[1, 4]], K)[0] == 2.0
+    # Monte Carlo over the hash: zero rows give all-zero codes; a zero and a nonzero row agree
+    # on a bit with rate 1/2
+    W = rng.standard_normal((d, R)).astype(np.float32)
+    codes, _ = oracle.hash_codes(np.stack([X[1], X[4], X[0]]), W, 1, R)
+    assert not codes[0].any() and not codes[1].any()
+    rate = float(np.mean(codes[0] == codes[2]))
+    assert abs(rate - 0.5) <= 5 * math.sqrt(0.25 / R), rate
+
+
 def table_sigma_bound(seed: int = 21):
     rng = np.random.default_rng(seed)
     K, L, d, n = 5, 8, 6, 700
@@ -372,4 +414,4 @@ def _clusters(rng, n, d):
 
 ALL = [saturating_counters, hand_examples, const_mode_is_non_strict, exact_signs, scale_negation, recount,
        identical_points, mean_closed_form, order_invariance, sigma_two_pass, deletion,
-       collision_law, unbiased, table_sigma_bound]
+       collision_law, unbiased, zero_vectors, table_sigma_bound]

@@ -92,6 +92,12 @@ def test_fp8_raw_signs_stay_inside_stated_bound(shape):
         X0 = heavy_tail_points_torch(2000, 512, seed=4, device="cuda")[0].cpu().numpy()
     W = projection_matrix(X0.shape[1], K, L, 6)
     X = adversarial_rows(X0, W, 1000, 1000, seed=10)
+    # rows whose largest value is below 2^-119: their scale 2^-e is beyond FP32 (e < -127),
+    # so the conversion must scale each value in one exact step
+    rng = np.random.default_rng(12)
+    tiny = (np.sign(rng.standard_normal((20, X.shape[1]))) * 2.0 ** -123 *
+            (1 + rng.random((20, X.shape[1])))).astype(np.float32)
+    X = np.concatenate([X, tiny], axis=0)
     ace = ACE(W, K, L, precision="fp8", refine=False)
     cg = codes_as_uint16(ace.hash(torch.from_numpy(X).cuda()))
     P, _ = oracle.project(X, W)

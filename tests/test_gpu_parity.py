@@ -163,6 +163,27 @@ def test_codes_entry_points_and_checkpoint():
     assert np.array_equal(S2a, S2b) and np.array_equal(S3a, S3b)
 
 
+def test_threshold_mean_past_int64():
+    """sum_j S2_j beyond 2^63 (Eq. dynadd's mean from the counts): n = INT32_MAX identical
+    points in L = 4 tables put n in one bucket of each, S2_j = n^2, sum_j S2_j = 4 n^2 > 2^63.
+    Every point scores n, so mu = n, and each table's count variance is 0."""
+    from paper_1706_06664_amd import ACE
+    K, L, d = 1, 4, 8
+    n = 2 ** 31 - 1
+    a = ACE(projection_matrix(d, K, L, 3), K, L)
+    counts = np.zeros((L, 2), np.int32)
+    counts[:, 1] = n
+    a.set_counts(counts, n)
+    S2, _ = a.table_stats()
+    assert [int(v) for v in S2] == [n * n] * L and L * n * n > 2 ** 63
+    th = a.threshold("const", 1.0)
+    assert th["n"] == n
+    assert abs(th["mu"] - n) <= 1e-12 * n, th["mu"]
+    assert th["sigma_table"] == 0.0
+    assert abs(th["tau"] - (n - 1)) <= 1e-12 * n
+    a.close()
+
+
 def test_error_paths():
     import torch
     from paper_1706_06664_amd import ACE, AceError

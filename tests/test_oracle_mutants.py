@@ -31,6 +31,8 @@ MUTANTS = [
     ("cap_one_too_high", "if (*a >= cap) {", "if (*a > cap) {"),
     ("capped_cube_uses_square", "cube += (u128)(after * after * after - before * before * before);",
      "cube += (u128)(after * after - before * before);"),
+    ("zero_vector_pair_never_collides", "p = 0.5;", "p = 0.0;"),
+    ("zero_pair_collides_half_the_time", "p = 1.0;", "p = 0.5;"),
     ("mean_divides_by_n_only", "out->mu = n > 0 ? (double)s2tot / ((double)n * (double)L) : 0.0;",
      "out->mu = n > 0 ? (double)s2tot / ((double)n) : 0.0;"),
 ]
