@@ -260,25 +260,28 @@ def test_bf16_chain_within_bound(I, seed, mode):
 
 # ---- e4m3 ----------------------------------------------------------------------------------
 
-def _tiny_e4m3(s):
-    """Two e4m3 values whose product is 1.875 2^-s (just below 2^{1-s})."""
-    for ea in range(-6, 9):
-        b = 2.0 ** (-s - ea)
-        if 2.0 ** -9 <= b <= 448:
-            return 1.875 * 2.0 ** ea, b
+def _e4m3_pair(s):
+    """A big e4m3 value g (product g^2) and two e4m3 values whose product is 1.875 2^-s g^2,
+    just below 2^{1-s} of the big product.  g grows past 1 only where the tiny product
+    would fall below what two e4m3 values can make."""
+    for eg in range(0, 9):
+        for ea in range(-6, 9):
+            b = 2.0 ** (2 * eg - s - ea)
+            if 2.0 ** -9 <= b <= 448:
+                return 2.0 ** eg, 1.875 * 2.0 ** ea, b
     raise ValueError(s)
 
 
 def _e4m3_case(big_positions, tiny_positions, s):
-    a_t, b_t = _tiny_e4m3(s)
+    g, a_t, b_t = _e4m3_pair(s)
     A = np.zeros((16, 128))
     for k in big_positions:
-        A[:, k] = 1.0
+        A[:, k] = g
     for k in tiny_positions:
         A[:, k] = a_t
     B = np.zeros((128, 16))
     for k in big_positions:
-        B[k, :] = 1.0
+        B[k, :] = g
     for k in tiny_positions:
         B[k, :] = b_t
     return A, B
@@ -319,8 +322,11 @@ def test_e4m3_chain_within_bound(I, seed, heavy):
     As, Bs = [], []
     for i in range(I):
         if heavy:
-            A = torch.from_numpy(rng.standard_t(3, (16, 128)).astype(np.float32) * 16).to(torch.float8_e4m3fn)
-            B = torch.from_numpy(rng.standard_t(3, (128, 16)).astype(np.float32) * 16).to(torch.float8_e4m3fn)
+            # clipped to the finite range first: the cast turns values past 448 into NaN
+            A = torch.from_numpy(np.clip(rng.standard_t(3, (16, 128)) * 16, -448, 448)
+                                 .astype(np.float32)).to(torch.float8_e4m3fn)
+            B = torch.from_numpy(np.clip(rng.standard_t(3, (128, 16)) * 16, -448, 448)
+                                 .astype(np.float32)).to(torch.float8_e4m3fn)
             A = e4m3_value(A.view(torch.uint8).numpy())
             B = e4m3_value(B.view(torch.uint8).numpy())
         else:
