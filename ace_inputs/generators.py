@@ -212,7 +212,7 @@ def drifting_mixture_rows(rid: int, n: int, d: int, seed: int = 5, n_means: int 
 
 def serving_trace(n_requests: int, d: int, seed: int = 5, median_batch: int = 256, sigma_log: float = 1.0,
                   max_batch: int = 65_536, rate_per_s: float = 1000.0, insert_frac: float = 0.7,
-                  pool_rows: int | None = None):
+                  pool_rows: int | None = None, n_override: dict | None = None):
     """Request log and host rows of the serving workload.
 
     Returns (kind int32 [R] with 0 = insert and 1 = score, n int64 [R], row0 int64 [R],
@@ -220,11 +220,14 @@ def serving_trace(n_requests: int, d: int, seed: int = 5, median_batch: int = 25
     outputs are packed: request r writes [out0, out0 + n).  With pool_rows=None every
     request has its own rows, drifting_mixture_rows(r, n), laid out in request order.
     Otherwise the pool holds pool_rows drifting rows (blocks of 16,384 rows, block b drawn as
-    request id 1000*b) and request r reads the window starting at a seeded offset."""
+    request id 1000*b) and request r reads the window starting at a seeded offset.
+    n_override {rid: rows} replaces the drawn sizes of the named requests."""
     reqs = serving_requests(n_requests, seed=seed, insert_frac=insert_frac, median_batch=median_batch,
                             sigma_log=sigma_log, max_batch=max_batch, rate_per_s=rate_per_s)
     kind = np.array([0 if q.kind == "insert" else 1 for q in reqs], np.int32)
     n = np.array([q.n for q in reqs], np.int64)
+    for rid, rows in (n_override or {}).items():
+        n[rid] = rows
     t = np.array([q.arrival_s for q in reqs], np.float64)
     out0 = np.zeros(n_requests, np.int64)
     sc = kind == 1

@@ -6,21 +6,25 @@ score every point (hash + gather-sum), compute the mean/std threshold and flag
 the points below it: the whole of Alg. 1 plus the Sec. 5.3 threshold over one
 synthetic batch that is already resident in HBM.
 
+Timing: W warm-up steps, then K steps each bracketed by HIP events on the launch
+stream with the library's own event profiling off; `ms_per_step` is the median.
+A separate profiled pass of the same steps gives the per-kernel launch times
+(roofline, HBM fractions and the phase split).
+
 Headline workload (the `value`): connection-log shaped points, 494,021 x 120
 (38 lognormal columns, 82 one-hot columns, 20% anomalies from rare clusters),
 K = 15 bits, L = 50 tables, FP32 projections refined in FP64 inside the FP32
-error bound.  Further fields: the same workload in split-BF16 mode, and a dense
-4,000,000 x 1024 low-rank workload (K = 15, L = 64) in FP32 and split-BF16 mode
-with refined fractions, raw flip rates and raw score errors, a heavy-tailed
-1,000,000 x 4096 workload (K = 16, L = 100) in FP32, split-BF16 and FP8, and the
-serving loop (d = 256, K = 15, L = 50): saturation rate and p50/p99 latency at
-fixed offered loads.
+error bound.  The other workloads (split-BF16 and e4m3 against FP32 on a dense
+4,000,000 x 1024 low-rank workload and a 1,000,000 x 4096 heavy-tailed one, the
+serving loop, the estimator study) go into a compact the benchmark spec block of the
+JSON line; their full records go to stderr and, with --detail PATH, to a file.
 
-Prints one JSON line.
+Prints one JSON line on stdout.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -28,11 +32,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
-KERNEL = {"fp32": "hash_fp32_direct_kernel", "bf16": "hash_bf16_kernel"}
+HBM_PEAK = 8.0e12
+HASH_KERNEL = {"fp32": "hash_fp32_direct_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def r4(x):
+    """Four significant digits (keeps the JSON line short)."""
+    if isinstance(x, float):
+        return float(f"{x:.4g}")
+    if isinstance(x, dict):
+        return {k: r4(v) for k, v in x.items()}
+    if isinstance(x, list):
+        return [r4(v) for v in x]
+    return x
 
 
 def recorded_traffic(source: str, summary: str):
@@ -52,11 +68,27 @@ def recorded_traffic(source: str, summary: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(X, W, K, L, target_s=12.0):
-    """The oracle, untuned, on a bounded prefix of the workload: hash + insert every sample
-    row, then hash + score + threshold + flags.  Returns points/s of that sample."""
+# ---- CPU baseline (the oracle, untuned) ------------------------------------------------------
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def oracle_step_rate(X, W, K, L, target_s):
+    """The oracle on a bounded prefix of the workload: hash + insert every sample row, then
+    hash + score + threshold + flags.  Returns (points/s, rows, seconds)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
     def run(m):
         t0 = time.perf_counter()
@@ -69,18 +101,71 @@ def cpu_baseline(X, W, K, L, target_s=12.0):
         sk.flags(T, th["tau"], oracle.MODE_SCORED)
         return time.perf_counter() - t0
 
-    m = 2000
+    m = 1000
     t = run(m)
     m2 = int(min(X.shape[0], max(m, m * target_s / max(t, 1e-3))))
     t2 = run(m2)
-    return {"value": m2 / t2, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {m2} of {X.shape[0]} rows of the headline workload, hash+insert then "
-                      f"hash+score+threshold+flags, {t2:.1f} s on {threads} OpenMP threads"}
+    return m2 / t2, m2, t2
+
+
+def cpu_baseline(X, W, K, L, target_s=10.0):
+    """All host threads, in this process; then one thread, in a child process (the oracle's
+    OpenMP team size is fixed when its library loads)."""
+    threads = oracle_threads()
+    v, m, t = oracle_step_rate(X, W, K, L, target_s)
+    out = {"value": v, "unit": "points/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"first {m} of {X.shape[0]} headline rows: hash+insert, then hash+score+threshold+flags, "
+                     f"{t:.1f} s on {threads} threads"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(target_s)], env=env,
+                           capture_output=True, text=True, timeout=600)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": one["value"], "cores": 1, "rows": one["rows"]}
+    except Exception as e:   # reported, never fatal: the GPU numbers stand on their own
+        out["one_core"] = {"error": str(e)[:200]}
+    return out
+
+
+def cpu_leg(target_s):
+    """Child process of cpu_baseline: the same oracle run on the threads OMP_NUM_THREADS gives."""
+    from ace_inputs import c2_points, projection_matrix
+    X, _ = c2_points()
+    W = projection_matrix(120, 15, 50, 1706066642)
+    v, m, t = oracle_step_rate(X, W, 15, 50, target_s)
+    print(json.dumps({"value": v, "rows": m, "seconds": t}), flush=True)
+
+
+def oracle_sample_check(Xd, W, K, L, codes_by_mode, rows):
+    """FP64 oracle hashing of the first `rows` rows (rows/s on the host threads), and the code
+    bits of each GPU mode on those rows that differ from the FP64 signs outside the oracle's
+    margin (the unrefined flips, which the refinement must bring to 0)."""
+    import numpy as np
+    import oracle
+    Xs = Xd[:rows].cpu().numpy()
+    t0 = time.perf_counter()
+    co, amb = oracle.hash_codes(Xs, W, K, L)
+    dt = time.perf_counter() - t0
+    out = {"rows": rows, "oracle_rows_per_s": rows / dt, "oracle_threads": oracle_threads(),
+           "ambiguous_bits": int(np.unpackbits(amb.view(np.uint8)).sum())}
+    for mode, cg in codes_by_mode.items():
+        diff = np.bitwise_and(np.bitwise_xor(cg, co), np.bitwise_not(amb))
+        out[f"{mode}_unrefined_flips"] = int(np.unpackbits(diff.view(np.uint8)).sum())
+    return out
+
+
+# ---- GPU workloads ---------------------------------------------------------------------------
+
+def median(v):
+    s = sorted(v)
+    m = len(s)
+    return s[m // 2] if m % 2 else 0.5 * (s[m // 2 - 1] + s[m // 2])
 
 
 def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, counter_bits=32, signs=None):
-    """Time `steps` full steps; return timing, per-kernel event timing and counters.
-    If `keep` is a dict, the last step's T (int32, device) is stored in keep["T"]."""
+    """Time `steps` full steps (median, HIP events on the launch stream, profiling off), then
+    profile as many steps again for the per-kernel launch times.  If `keep` is a dict, the
+    last step's T (int32, device) is stored in keep["T"]."""
     import torch
     from paper_1706_06664_amd import ACE
     n, d = Xd.shape
@@ -88,6 +173,7 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     T = torch.empty(n, dtype=torch.int32, device=Xd.device)
     ace = ACE(W if signs is None else None, K, L, precision=precision, device=0, refine=refine,
               counter_bits=counter_bits, signs=signs, d=d)
+    st = torch.cuda.current_stream()
 
     def step():
         ace.reset()
@@ -99,45 +185,85 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(st)
+        flags, th = step()
+        e1.record(st)
+    torch.cuda.synchronize()
+    times = [e0.elapsed_time(e1) for e0, e1 in ev]
+    # profiled pass: HIP events around every launch, on its stream
     ace.profile()
     c0 = ace.counters()
     ace.profile_enable(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        flags, th = step()
+        step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    prof_ms = (time.perf_counter() - t0) * 1e3 / steps
     ace.profile_enable(False)
     prof = ace.profile()
     c1 = ace.counters()
     ace.close()
     if keep is not None:
         keep["T"] = T
-    ms = (t1 - t0) * 1e3 / steps
+    ms = median(times)
     hash_ms = prof["hash_ms"] / max(1, prof["hash_launches"])
     rows = prof["hash_rows"] / max(1, prof["hash_launches"])
     flop = 2.0 * rows * d * K * L
     executed = flop * (16.0 / K) * (3.0 if precision == "bf16" else 1.0)
-    kernel = {"fp32": "hash_fp32_direct_kernel", "bf16": "hash_bf16_kernel", "fp8": "hash_fp8_kernel"}[precision]
-    if signs is not None:
-        kernel = "hash_struct_kernel"
+    kernel = HASH_KERNEL[precision] if signs is None else "hash_struct_kernel"
     ach = flop / (hash_ms / 1e3)
     bits = c1["bits_hashed"] - c0["bits_hashed"]
+
+    def per_launch(key):
+        return prof[f"{key}_ms"] / max(1, prof[f"{key}_launches"])
+
+    # HBM fractions of the count kernels (a5, a6) and the convert (a1): algorithmic bytes
+    # per launch over the average launch time.  Rows per launch from the launch counts.
+    hbm = {}
+    tables = float(L) * (1 << K) * (2 if counter_bits == 16 else 4)
+    if prof["update_launches"]:
+        r_u = n * steps / prof["update_launches"]
+        b = 2.0 * L * r_u + 2.0 * tables
+        hbm["update"] = {"ms": per_launch("update"), "bytes": b, "frac": b / (per_launch("update") / 1e3) / HBM_PEAK}
+    if prof["score_launches"]:
+        r_s = n * steps / prof["score_launches"]
+        b = (2.0 * L + 8.0) * r_s + tables
+        hbm["score"] = {"ms": per_launch("score"), "bytes": b, "frac": b / (per_launch("score") / 1e3) / HBM_PEAK}
+    if prof["convert_launches"]:
+        r_c = 2.0 * n * steps / prof["convert_launches"]
+        out_b = {"bf16": 4.0 * d, "fp8": 1.0 * d}.get(precision, 0.0)
+        b = (4.0 * d + out_b + 12.0) * r_c
+        hbm["convert"] = {"ms": per_launch("convert"), "bytes": b,
+                          "frac": b / (per_launch("convert") / 1e3) / HBM_PEAK}
     return {
-        "points_per_s": n / (ms / 1e3), "ms_per_step": ms,
+        "points_per_s": n / (ms / 1e3), "ms_per_step": ms, "ms_per_step_mean": sum(times) / len(times),
+        "ms_per_step_min": min(times), "ms_per_step_max": max(times), "ms_per_step_profiled": prof_ms,
         "phase_ms_per_step": {k: prof[k] / steps for k in ("convert_ms", "hash_ms", "refine_ms", "update_ms",
                                                             "score_ms", "other_ms")},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[precision] / 1e12, "unit": "TFLOP/s",
                      "frac": ach / PEAK[precision], "traffic": None, "kernel": kernel,
                      "avg_launch_ms": hash_ms, "rows_per_launch": rows,
                      "executed_frac": executed / (hash_ms / 1e3) / PEAK[precision]},
+        "hbm": hbm,
         "refined_bit_frac": (c1["bits_refined"] - c0["bits_refined"]) / max(1, bits),
         "raw_flip_rate": (c1["bits_flipped"] - c0["bits_flipped"]) / max(1, bits),
         "in_bound_unrefined_frac": (c1["bits_in_bound_unrefined"] - c0["bits_in_bound_unrefined"]) / max(1, bits),
         "saturated_increments_last_step": c1["saturated_increments"],
         "flagged": int(flags.sum().item()), "tau": th["tau"],
     }
+
+
+def brief(r):
+    """The fields of a run_workload record that the JSON line keeps."""
+    out = {"ms": r["ms_per_step"], "pts_s": r["points_per_s"], "proj_frac": r["roofline"]["frac"],
+           "refined": r["refined_bit_frac"]}
+    if r["roofline"]["kernel"] == "hash_bf16_kernel":
+        out["proj_exec_frac"] = r["roofline"]["executed_frac"]
+    if r["raw_flip_rate"]:
+        out["raw_flips"] = r["raw_flip_rate"]
+    return out
 
 
 def cache_codes_run(Xd, W, K, L, steps, warmup):
@@ -147,6 +273,7 @@ def cache_codes_run(Xd, W, K, L, steps, warmup):
     import torch
     from paper_1706_06664_amd import ACE
     ace = ACE(W, K, L, precision="fp32", device=0)
+    st = torch.cuda.current_stream()
 
     def step():
         ace.reset()
@@ -159,13 +286,15 @@ def cache_codes_run(Xd, W, K, L, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        flags = step()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(st)
+        step()
+        e1.record(st)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ms = median([e0.elapsed_time(e1) for e0, e1 in ev])
     ace.close()
-    return {"points_per_s": Xd.shape[0] / (ms / 1e3), "ms_per_step": ms, "flagged": int(flags.sum().item()),
+    return {"points_per_s": Xd.shape[0] / (ms / 1e3), "ms_per_step": ms,
             "step": "hash once, insert codes, score codes, threshold, flags"}
 
 
@@ -192,7 +321,6 @@ def raw_score_error(Xs, W, K, L, precision):
     """Score error of raw low-precision signs (refinement off) against the refined scores,
     which equal the FP64 oracle's (checked by the GPU tests): insert and score the sample."""
     import numpy as np
-    import torch
     from paper_1706_06664_amd import ACE
     out = []
     for refine in (True, False):
@@ -215,14 +343,47 @@ def popcount_xor(a, b):
     return int(table[x.long()].sum().item())
 
 
-def heavy_tail_runs(steps):
+def sample_codes(ace_args, Xs):
+    """Codes of the sample rows as host uint16 [rows][L]."""
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    a = ACE(*ace_args[:3], **ace_args[3])
+    c = codes_as_uint16(a.hash(Xs))
+    a.close()
+    return c
+
+
+def low_rank_runs(n3, steps, warmup, sample_rows):
+    """Dense low-rank 4,000,000 x 1024 rows, K = 15, L = 64: FP32 and split-BF16 refined steps,
+    the raw-sign score error, and the oracle's check of a 65,536-row sample."""
+    import torch
+    from ace_inputs import low_rank_points_torch, projection_matrix
+    d3, K3, L3 = 1024, 15, 64
+    X3, _ = low_rank_points_torch(n3, d3, seed=3, device="cuda:0")
+    W3 = projection_matrix(d3, K3, L3, 1706066643)
+    lr = {"workload": f"low-rank {n3}x{d3}, K={K3}, L={L3}"}
+    for prec in ("fp32", "bf16"):
+        log(f"low-rank {n3}x{d3} {prec}: warmup {warmup}, steps {steps}")
+        lr[prec] = run_workload(X3, W3, K3, L3, prec, steps, warmup)
+        log(f"  {lr[prec]['ms_per_step']:.3f} ms/step (profiled {lr[prec]['ms_per_step_profiled']:.3f})")
+    lr["bf16_speedup"] = lr["fp32"]["ms_per_step"] / lr["bf16"]["ms_per_step"]
+    Xs = X3[:sample_rows].contiguous()
+    lr["bf16_raw_score_error"] = raw_score_error(Xs, W3, K3, L3, "bf16")
+    codes = {m: sample_codes((W3, K3, L3, {"precision": m}), Xs) for m in ("fp32", "bf16")}
+    log(f"low-rank oracle sample: {sample_rows} rows")
+    lr["oracle_sample"] = oracle_sample_check(X3, W3, K3, L3, codes, sample_rows)
+    log(f"  {lr['oracle_sample']}")
+    del X3, Xs
+    torch.cuda.empty_cache()
+    return lr
+
+
+def heavy_tail_runs(steps, warmup, sample_rows):
     """Heavy-tailed 1,000,000 x 4096 rows, K = 16, L = 100: FP32 and split-BF16 refined steps,
     and FP8 e4m3 with raw signs (refine = 2 also counts the bits inside the FP8 bound).  The
     FP8 raw flip rate and score error are taken against the FP32 refined codes and scores,
-    which equal the FP64 signs (GPU tests)."""
-    import numpy as np
+    which equal the FP64 signs (GPU tests, and the oracle sample here)."""
     import torch
-    from ace_inputs import heavy_tail_points_torch, projection_matrix
+    from ace_inputs import heavy_tail_points_torch, projection_matrix, structured_signs
     from paper_1706_06664_amd import ACE
     n4, d4, K4, L4 = 1_000_000, 4096, 16, 100
     X4, _ = heavy_tail_points_torch(n4, d4, seed=4, device="cuda:0")
@@ -230,9 +391,9 @@ def heavy_tail_runs(steps):
     out = {"workload": f"heavy-tail t(3) {n4}x{d4}, K={K4}, L={L4}"}
     keep = {}
     for prec, refine in (("fp32", 1), ("bf16", 1), ("fp8", 2)):
-        log(f"heavy-tail {n4}x{d4} {prec} refine={refine}: steps {steps}")
+        log(f"heavy-tail {n4}x{d4} {prec} refine={refine}: warmup {warmup}, steps {steps}")
         k = {}
-        out[prec] = run_workload(X4, W4, K4, L4, prec, steps, 1, refine=refine, keep=k)
+        out[prec] = run_workload(X4, W4, K4, L4, prec, steps, warmup, refine=refine, keep=k)
         keep[prec] = k["T"].clone()
         log(f"  {out[prec]['ms_per_step']:.3f} ms/step")
     c32 = ACE(W4, K4, L4, precision="fp32").hash(X4)
@@ -247,13 +408,18 @@ def heavy_tail_runs(steps):
     out["fp8_in_bound_frac"] = out["fp8"]["in_bound_unrefined_frac"]
     out["bf16_speedup"] = out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"]
     out["fp8_raw_speedup"] = out["fp32"]["ms_per_step"] / out["fp8"]["ms_per_step"]
+    del c32, c8
+    Xs = X4[:sample_rows].contiguous()
+    codes = {m: sample_codes((W4, K4, L4, {"precision": m}), Xs) for m in ("fp32", "bf16")}
+    log(f"heavy-tail oracle sample: {sample_rows} rows")
+    out["oracle_sample"] = oracle_sample_check(X4, W4, K4, L4, codes, sample_rows)
+    log(f"  {out['oracle_sample']}")
     # Structured projections (H D3 H D2 H D1, one 4096-point block per row): another hash
     # family (the paper's fast-transform hashing), refined to the FP64 signs of its own
     # dense equivalent.
-    from ace_inputs import structured_signs
     s4, _ = structured_signs(d4, K4, L4, 1706066647)
     log(f"heavy-tail {n4}x{d4} structured fp32: steps {steps}")
-    st = run_workload(X4, None, K4, L4, "fp32", steps, 1, signs=s4)
+    st = run_workload(X4, None, K4, L4, "fp32", steps, warmup, signs=s4)
     rows = st["roofline"]["rows_per_launch"]
     st["roofline"] = {"bound": "hbm", "kernel": "hash_struct_kernel", "avg_launch_ms": st["roofline"]["avg_launch_ms"],
                       "achieved": 4.0 * d4 * rows / (st["roofline"]["avg_launch_ms"] / 1e3) / 1e9, "peak": 8000.0,
@@ -262,7 +428,7 @@ def heavy_tail_runs(steps):
     out["structured_fp32"] = st
     out["structured_speedup_vs_fp32"] = out["fp32"]["ms_per_step"] / st["ms_per_step"]
     log(f"  {st['ms_per_step']:.3f} ms/step")
-    del X4, c32, c8
+    del X4, Xs
     torch.cuda.empty_cache()
     return out
 
@@ -378,25 +544,78 @@ def exact_score_runs(X, W, K, n_queries=4096, reps=5):
     return out
 
 
+def north_star_block(extra):
+    """The compact summary the JSON line carries: BF16-vs-FP32 speed-ups with refined
+    fractions, raw flip rates and the unrefined flips the oracle sample found, the e4m3 flip
+    rate and score error, and the serving loop's rates and latencies."""
+    ns = {}
+    lr = extra.get("low_rank_1024")
+    if lr:
+        ns["low_rank_4000000x1024"] = {
+            "bf16_vs_fp32": lr["bf16_speedup"], "fp32": brief(lr["fp32"]), "bf16": brief(lr["bf16"]),
+            "bf16_hbm_convert_frac": lr["bf16"]["hbm"].get("convert", {}).get("frac"),
+            "bf16_raw_score_err": {"mean": lr["bf16_raw_score_error"]["mean_rel"],
+                                   "max": lr["bf16_raw_score_error"]["max_rel"]},
+            "oracle_sample": {k: v for k, v in lr["oracle_sample"].items() if k != "oracle_threads"}}
+    ht = extra.get("heavy_tail_4096")
+    if ht:
+        ns["heavy_tail_1000000x4096"] = {
+            "bf16_vs_fp32": ht["bf16_speedup"], "fp32": brief(ht["fp32"]), "bf16": brief(ht["bf16"]),
+            "e4m3_raw": {"ms": ht["fp8"]["ms_per_step"], "vs_fp32": ht["fp8_raw_speedup"],
+                         "proj_frac": ht["fp8"]["roofline"]["frac"], "flip_rate": ht["fp8_raw_flip_rate"],
+                         "score_err_mean": ht["fp8_raw_score_error"]["mean_rel"],
+                         "score_err_max": ht["fp8_raw_score_error"]["max_rel"], "in_bound": ht["fp8_in_bound_frac"]},
+            "structured": {"ms": ht["structured_fp32"]["ms_per_step"], "vs_fp32": ht["structured_speedup_vs_fp32"]},
+            "oracle_sample": {k: v for k, v in ht["oracle_sample"].items() if k != "oracle_threads"}}
+    if "connection_log_bf16" in extra:
+        ns["connection_log_bf16"] = dict(brief(extra["connection_log_bf16"]),
+                                         vs_fp32=extra["connection_log_bf16_speedup"])
+    if "connection_log_cache_codes" in extra:
+        ns["connection_log_hash_once"] = {"ms": extra["connection_log_cache_codes"]["ms_per_step"],
+                                          "pts_s": extra["connection_log_cache_codes"]["points_per_s"]}
+    if "connection_log_counters16" in extra:
+        ns["connection_log_counters16"] = {"ms": extra["connection_log_counters16"]["ms_per_step"]}
+    for key in ("serving_256", "serving_256_graphs"):
+        sv = extra.get(key)
+        if sv:
+            ns[key] = {"closed_pts_s": {"fp32": sv["closed_loop_fp32"]["points_per_s"],
+                                        "bf16": sv["closed_loop_bf16"]["points_per_s"]},
+                       "open_bf16": [{"load": o["load"], "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
+                                      "pts_s": o["points_per_s"]} for o in sv["open_loop_bf16"]],
+                       "requests": sv["workload"].split(": ")[1].split(",")[0]}
+    ex = extra.get("exact_score_connection_log")
+    if ex:
+        ns["exact_S"] = {"ms": ex["ms_per_launch"], "fp64_mfma_frac": ex["roofline"]["frac"]}
+    return r4(ns)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--headline-only", action="store_true", help="skip the BF16 and 1024-d runs")
+    ap.add_argument("--headline-only", action="store_true", help="skip every workload but the headline")
     ap.add_argument("--low-rank-n", type=int, default=4_000_000)
+    ap.add_argument("--sample-rows", type=int, default=65_536,
+                    help="rows of the low-rank and heavy-tail workloads the oracle hashes")
+    ap.add_argument("--detail", default=None, help="write every record to this JSON file")
+    ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--traffic-run", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration), then two headline inserts "
                          "and scores; prints no JSON")
     args = ap.parse_args()
+    if args.cpu_leg is not None:
+        cpu_leg(args.cpu_leg)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout "
               f"is a design, not a run)", file=sys.stderr)
         sys.exit(2)
+    steps, warmup = max(1, args.steps), max(0, args.warmup)
 
     import torch
-    from ace_inputs import c2_points, low_rank_points_torch, projection_matrix
+    from ace_inputs import c2_points, projection_matrix
 
     K, L, d = 15, 50, 120
     X, _ = c2_points()
@@ -417,48 +636,38 @@ def main():
         torch.cuda.synchronize()
         log("traffic run done: copy 256 MiB, 2 x (insert + score) of the headline workload")
         return
-    log(f"connection-log {n}x{d} fp32: warmup {args.warmup}, steps {args.steps}")
-    head = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup)
-    log(f"  {head['ms_per_step']:.3f} ms/step")
+    log(f"connection-log {n}x{d} fp32: warmup {warmup}, steps {steps}")
+    head = run_workload(Xd, W, K, L, "fp32", steps, warmup)
+    log(f"  {head['ms_per_step']:.3f} ms/step median (mean {head['ms_per_step_mean']:.3f}, "
+        f"profiled {head['ms_per_step_profiled']:.3f})")
 
     extra = {}
     if not args.headline_only:
         log("connection-log bf16")
-        b = run_workload(Xd, W, K, L, "bf16", args.steps, args.warmup)
+        b = run_workload(Xd, W, K, L, "bf16", steps, warmup)
         extra["connection_log_bf16"] = b
         extra["connection_log_bf16_speedup"] = head["ms_per_step"] / b["ms_per_step"]
         log(f"  {b['ms_per_step']:.3f} ms/step")
         from ace_inputs import structured_signs
         s2, _ = structured_signs(d, K, L, 1706066646)
         log("connection-log structured fp32")
-        extra["connection_log_structured"] = run_workload(Xd, None, K, L, "fp32", args.steps, args.warmup, signs=s2)
+        extra["connection_log_structured"] = run_workload(Xd, None, K, L, "fp32", steps, warmup, signs=s2)
         log(f"  {extra['connection_log_structured']['ms_per_step']:.3f} ms/step")
         log("connection-log fp32, rows hashed once per step")
-        extra["connection_log_cache_codes"] = cache_codes_run(Xd, W, K, L, args.steps, args.warmup)
+        extra["connection_log_cache_codes"] = cache_codes_run(Xd, W, K, L, steps, warmup)
         log(f"  {extra['connection_log_cache_codes']['ms_per_step']:.3f} ms/step")
         log("paper-shape context runs")
-        extra["paper_shapes"] = paper_shape_runs(args.steps, args.warmup)
+        extra["paper_shapes"] = paper_shape_runs(steps, warmup)
         log("connection-log fp32, 16-bit counters")
-        c16 = run_workload(Xd, W, K, L, "fp32", args.steps, args.warmup, counter_bits=16)
+        c16 = run_workload(Xd, W, K, L, "fp32", steps, warmup, counter_bits=16)
         extra["connection_log_counters16"] = c16
         log(f"  {c16['ms_per_step']:.3f} ms/step, {c16['saturated_increments_last_step']} saturated increments")
         del Xd
         torch.cuda.empty_cache()
-        n3, d3, K3, L3 = args.low_rank_n, 1024, 15, 64
-        X3, _ = low_rank_points_torch(n3, d3, seed=3, device="cuda:0")
-        W3 = projection_matrix(d3, K3, L3, 1706066643)
-        lr = {"workload": f"low-rank {n3}x{d3}, K={K3}, L={L3}"}
-        steps3 = max(2, args.steps // 4)
-        for prec in ("fp32", "bf16"):
-            log(f"low-rank {n3}x{d3} {prec}: steps {steps3}")
-            lr[prec] = run_workload(X3, W3, K3, L3, prec, steps3, 1)
-            log(f"  {lr[prec]['ms_per_step']:.3f} ms/step")
-        lr["bf16_speedup"] = lr["fp32"]["ms_per_step"] / lr["bf16"]["ms_per_step"]
-        lr["bf16_raw_score_error"] = raw_score_error(X3[:65536].contiguous(), W3, K3, L3, "bf16")
-        extra["low_rank_1024"] = lr
-        del X3
-        torch.cuda.empty_cache()
-        extra["heavy_tail_4096"] = heavy_tail_runs(max(2, args.steps // 8))
+        # the large workloads: at least 10 timed steps after 3 warm-ups (median)
+        big_steps, big_warm = max(10, steps // 2), max(3, warmup)
+        extra["low_rank_1024"] = low_rank_runs(args.low_rank_n, big_steps, big_warm, args.sample_rows)
+        extra["heavy_tail_4096"] = heavy_tail_runs(big_steps, big_warm, args.sample_rows)
         extra["serving_256"] = serving_runs()
         log("serving with captured graphs")
         extra["serving_256_graphs"] = serving_runs(graphs=True)
@@ -468,24 +677,28 @@ def main():
 
     base = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
+        log("cpu baseline (oracle): all host threads, then one")
         base = cpu_baseline(X, W, K, L)
+        log(f"  {base['value']:.3e} points/s on {base['cores']} threads; one core: {base['one_core']}")
 
     roof = dict(head["roofline"])
     tb = recorded_traffic("paper_1706_06664_amd/csrc/hash_fp32.hip",
                           "profiles/hash_fp32_direct_kernel__connection_log_494021x120.md")
+    roof["traffic"] = tb
     if tb is not None:
-        roof["traffic"] = tb
         roof["traffic_unit"] = "bytes/launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)"
         roof["algorithmic_bytes"] = 4.0 * n * d + 2.0 * n * L + 4.0 * d * K * L
+    roof.pop("rows_per_launch", None)
     out = {
         "metric": "points/s insert+score (K=15,L=50)",
         "value": head["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": head["ms_per_step"],
+        "ms_per_step_mean": head["ms_per_step_mean"],
+        "timing": "median of the timed steps, HIP events on the launch stream, library profiling off",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -493,15 +706,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "connection-log 494021x120, K=15, L=50, FP32 + FP64 refine",
                    "n": n, "d": d, "K": K, "L": L, "precision": "fp32", "refine": True},
-        "roofline": roof,
-        "cpu_baseline": base,
-        "phase_ms_per_step": head["phase_ms_per_step"],
-        "refined_bit_frac": head["refined_bit_frac"],
+        "roofline": r4(roof),
+        "cpu_baseline": r4(base) if base else None,
+        "hbm": r4({k: {"kernel": {"update": "update_lds_kernel", "score": "score_kernel"}.get(k, k), "ms": v["ms"],
+                       "frac": v["frac"]} for k, v in head["hbm"].items()}),
+        "phase_ms_per_step": r4(head["phase_ms_per_step"]),
+        "refined_bit_frac": r4(head["refined_bit_frac"]),
         "flagged": head["flagged"],
-        "tau": head["tau"],
     }
-    out.update(extra)
-    print(json.dumps(out), flush=True)
+    if extra:
+        out["north_star"] = north_star_block(extra)
+    line = json.dumps(out, separators=(",", ":"))
+    if args.detail:
+        with open(args.detail, "w") as f:
+            json.dump({"headline": head, **extra, "cpu_baseline": base}, f, indent=1, default=float)
+    log(f"detail: {json.dumps(r4(extra), separators=(',', ':'))}")
+    if len(line) > 8000:
+        log(f"warning: JSON line is {len(line)} bytes")
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

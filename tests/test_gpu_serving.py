@@ -194,3 +194,67 @@ def test_server_errors():
     srv2.close()
     assert ace.threshold("const", 1.0)["n"] == 10
     ace.close()
+
+
+_BIG = {37: 24000, 120: 65536, 121: 9000, 250: 40000, 251: 17000, 333: 33333}
+_bench_cache = {}
+
+
+def _bench_shape_trace():
+    """400 requests of the serving workload (d = 256, lognormal sizes, median 256) with six
+    requests forced to 9,000-65,536 rows, and their sequential oracle replay (cached)."""
+    if not _bench_cache:
+        K, L, d = 15, 50, 256
+        kind, n, row0, out0, t, pool = serving_trace(400, d, seed=5, n_override=_BIG)
+        W = projection_matrix(d, K, L, 1706066645)
+        T_o, sk, n_amb = _oracle_replay(kind, n, row0, out0, pool, W, K, L)
+        _bench_cache.update(kind=kind, n=n, row0=row0, out0=out0, t=t, pool=pool, W=W, T_o=T_o, sk=sk,
+                            n_amb=n_amb)
+    return _bench_cache
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_serving_bench_configuration(graphs):
+    """The configuration the serving benchmark runs: BF16 + refine, d = 256, K = 15, L = 50,
+    8 slots, max_rows = 65,536, batch_rows = 4,096, pinned rows.  Requests above batch_rows
+    form batches of their own, so the count-update path for large batches (LDS histogram,
+    codes at a row stride of the graph bucket) and the graph buckets of 16,384, 32,768 and
+    65,536 rows are captured, replayed and compared with the sequential oracle replay."""
+    import torch
+    from paper_1706_06664_amd import ACE
+    K, L = 15, 50
+    c = _bench_shape_trace()
+    kind, n, row0, out0, T_o, sk = c["kind"], c["n"], c["row0"], c["out0"], c["T_o"], c["sk"]
+    assert c["n_amb"] == 0
+    _say(dict(graphs=graphs, requests=len(kind), rows=int(n.sum()), largest=int(n.max()), scored=int(T_o.size)))
+    ace = ACE(c["W"], K, L, precision="bf16", refine=True)
+    srv = ace.server(slots=8, max_rows=65_536, gather_max_bytes=65_536, batch_rows=4096, graphs=graphs)
+    s_out = np.full(T_o.size, -1.0, np.float32)
+    T_out = np.zeros(T_o.size, np.uint32)
+    src = torch.from_numpy(c["pool"]).pin_memory()
+    # twice through the same server: the second replay reuses every captured graph
+    for rep in range(2):
+        if rep:
+            ace.reset()
+            torch.cuda.synchronize()   # the reset runs on this stream, the batches on the slots'
+            srv.reset_stats()
+            s_out[:] = -1.0
+            T_out[:] = 0
+        srv.replay(_records(kind, n, row0, out0, np.zeros_like(c["t"])), src, s_out, T_out, pinned=True)
+        st = srv.stats()
+        _say(st)
+        assert st["requests"] == len(kind) and st["rows"] == int(n.sum())
+        if graphs:
+            assert st["graph_launches"] == st["batches"]
+            # buckets above 8,192 rows: 16,384 (9,000 and 17,000 rows), 32,768, 65,536
+            assert st["graph_captures"] >= (4 if rep == 0 else 0)
+        np.testing.assert_array_equal(T_out.astype(np.int64), T_o)
+        np.testing.assert_allclose(s_out, T_o / L, rtol=1e-6, atol=0)
+        assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+        th = ace.threshold("scored", 1.0)
+        _, th_o = sk.threshold(oracle.MODE_SCORED, 1.0)
+        assert th["n"] == th_o["n"] and th["m_scored"] == th_o["m_scored"]
+        assert abs(th["mu"] - th_o["mu"]) <= 1e-12 * th_o["mu"]
+        assert abs(th["sigma"] - th_o["sigma"]) <= 1e-12 * max(th_o["sigma"], 1e-300)
+    srv.close()
+    ace.close()
