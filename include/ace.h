@@ -197,6 +197,23 @@ ace_status ace_flag(ace_ctx ctx, const uint32_t* T_dev, int64_t n, double tau, i
 ace_status ace_hash(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_dev,
                     uint16_t* refined_dev, void* stream);
 
+/* ace_hash for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same codes and refined masks as
+ * ace_hash, bit for bit, but it calls no hipMalloc, hipFree or allocating routine (ace_hash
+ * allocates the refined-mask staging on its first request for one).  Its scratch - the queue
+ * of uncertain projections and its counter, the code and mask staging, the converted BF16 or
+ * e4m3 rows and their norms - is one static 64 MiB device array per GPU, resolved when the
+ * first context on that GPU is created and held until the process ends.  Rows are hashed in
+ * chunks that fit the array (a multiple of 256 rows), so any n works; ACE_E_INVALID if not
+ * even 256 rows of this context fit (BF16 needs 4 DP bytes per row, e4m3 DP bytes, plus 8 L
+ * bytes for codes, masks and queue).  Every call on a GPU shares that GPU's array, whichever
+ * context it uses: calls that overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  The queue counter and the masks are cleared by fill
+ * kernels at the start of every chunk, so a call does not depend on what an earlier call
+ * left in the array.  Stream-ordered; other arguments and errors as ace_hash. */
+ace_status ace_hash_static(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_dev,
+                           uint16_t* refined_dev, void* stream);
+
 /* Counting phase from precomputed codes (uint16 [L][n] device, values < 2^K). */
 ace_status ace_insert_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, void* stream);
 

@@ -31,7 +31,7 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
-           "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe"]
+           "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe", "ace_hash_static"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "ace_threshold": [P, i32, f64, P, ctypes.POINTER(Thresh)],
         "ace_flag": [P, P, i64, f64, i32, P, P],
         "ace_hash": [P, P, i64, P, P, P],
+        "ace_hash_static": [P, P, i64, P, P, P],
         "ace_insert_codes": [P, P, i64, P],
         "ace_score_codes": [P, P, i64, P, P, P],
         "ace_get_counts": [P, P],
@@ -263,6 +264,16 @@ class ACE:
         ref = torch.empty((self.L, n), dtype=torch.int16, device=X.device) if want_refined else None
         _check(self.lib.ace_hash(self.h, p, n, codes.data_ptr(), ref.data_ptr() if ref is not None else None,
                                  _stream_ptr(stream)), "ace_hash")
+        return (codes, ref) if want_refined else codes
+
+    def hash_static(self, X, want_refined: bool = False, stream=None):
+        """As hash(), through ace_hash_static (no device allocation inside the call)."""
+        import torch
+        p, n = self._rows(X)
+        codes = torch.empty((self.L, n), dtype=torch.int16, device=X.device)
+        ref = torch.empty((self.L, n), dtype=torch.int16, device=X.device) if want_refined else None
+        _check(self.lib.ace_hash_static(self.h, p, n, codes.data_ptr(), ref.data_ptr() if ref is not None else None,
+                                        _stream_ptr(stream)), "ace_hash_static")
         return (codes, ref) if want_refined else codes
 
     def insert_codes(self, codes, stream=None):

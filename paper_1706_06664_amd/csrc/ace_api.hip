@@ -448,6 +448,9 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
         }
         attrs_done = true;
     }
+    // The allocation-free entry point's scratch on this device; a failure here is reported
+    // by that entry point, which retries the binding.
+    (void)scratch_bind(cfg->device);
 
     ace_ctx c = new (std::nothrow) ace_ctx_s();
     if (!c) return ACE_E_NOMEM;

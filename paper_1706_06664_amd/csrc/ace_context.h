@@ -85,5 +85,8 @@ ace_status check(ace_ctx c, hipError_t e);
 // for n rows serves any smaller batch.  count_bits: add n K L to the hashed-bit counter.
 ace_status hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s,
                       const int64_t* n_dev = nullptr, bool count_bits = true);
+// Resolve, once per device, the device address of the static scratch array that
+// ace_hash_static uses (the device must be current).
+ace_status scratch_bind(int device);
 
 }  // namespace ace
