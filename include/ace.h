@@ -136,8 +136,9 @@ typedef struct {
                                           last reset */
 } ace_counters;
 
-/* Create a context on cfg->device: copies W (host, FP32 [d][K*L]) and zeroes the L x 2^K
- * counts (int32, or uint16 with counter_bits = 16).  Returns ACE_E_INVALID for out-of-range fields or NULL pointers,
+/* Hash initialisation of Alg. 1 (K*L projection vectors drawn once and stored, Sec. 3.4
+ * costs their storage): create a context on cfg->device, copy W (host, FP32 [d][K*L]) and
+ * zero the L x 2^K counts (int32, or uint16 with counter_bits = 16).  Returns ACE_E_INVALID for out-of-range fields or NULL pointers,
  * ACE_E_NOMEM if allocation fails or exceeds cfg->mem_budget, ACE_E_DEVICE if the
  * device cannot be used.  *out is set only on success. */
 ace_status ace_create(const ace_config* cfg, const float* W_host, ace_ctx* out);
@@ -158,10 +159,12 @@ ace_status ace_create_structured(const ace_config* cfg, const uint8_t* signs, ac
  * ACE_E_STATE (nothing freed) while a serving loop is attached (ace_server_create). */
 ace_status ace_destroy(ace_ctx ctx);
 
-/* Zero the counts, the per-table sums and the scored set (stream-ordered). */
+/* Back to the empty sketch Alg. 1 starts from: zero the counts, the per-table sums and the
+ * scored set (stream-ordered). */
 ace_status ace_reset(ace_ctx ctx, void* stream);
 
-/* Zero only the scored set's moments (stream-ordered). */
+/* Start a new scored set for the Sec. 5.3 threshold (mean and deviation of the scores):
+ * zero only its moments (stream-ordered). */
 ace_status ace_reset_scored(ace_ctx ctx, void* stream);
 
 /* Counting phase of Alg. 1: hash the n rows of X_dev and add each to its bucket in every
@@ -186,12 +189,14 @@ ace_status ace_score(ace_ctx ctx, const float* X_dev, int64_t n, float* s_dev, u
  * set is empty (no inserted points, or no scored points for ACE_THR_SCORED). */
 ace_status ace_threshold(ace_ctx ctx, int32_t mode, double alpha, void* stream, ace_thresh* out);
 
-/* flags_dev[i] = 1 iff s_i = T_dev[i] / L is reported: s < tau for ACE_THR_SCORED and
+/* Reporting step of Alg. 1 (s <= mu - alpha) and of Sec. 5.3 (s below mean minus one
+ * standard deviation): flags_dev[i] = 1 iff s_i = T_dev[i] / L is reported: s < tau for ACE_THR_SCORED and
  * ACE_THR_TABLE, s <= tau for ACE_THR_CONST.  uint8 [n]. */
 ace_status ace_flag(ace_ctx ctx, const uint32_t* T_dev, int64_t n, double tau, int32_t mode,
                     uint8_t* flags_dev, void* stream);
 
-/* Hash only: codes_dev receives uint16 [L][n] (table-major: code of row i in table j at
+/* The hash functions alone: the K*L signs of Sec. 2.1 concatenated into L K-bit codes
+ * (Sec. 3.2).  codes_dev receives uint16 [L][n] (table-major: code of row i in table j at
  * j*n + i).  refined_dev (same shape, may be NULL) receives, per code, the mask of bits that
  * were recomputed in FP64.  Does not touch the counts. */
 ace_status ace_hash(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_dev,
@@ -214,25 +219,27 @@ ace_status ace_hash(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_
 ace_status ace_hash_static(ace_ctx ctx, const float* X_dev, int64_t n, uint16_t* codes_dev,
                            uint16_t* refined_dev, void* stream);
 
-/* Counting phase from precomputed codes (uint16 [L][n] device, values < 2^K). */
+/* Counting phase of Alg. 1 from precomputed codes (uint16 [L][n] device, values < 2^K). */
 ace_status ace_insert_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, void* stream);
 
-/* Query phase from precomputed codes (uint16 [L][n] device). */
+/* Query phase of Alg. 1 from precomputed codes (uint16 [L][n] device). */
 ace_status ace_score_codes(ace_ctx ctx, const uint16_t* codes_dev, int64_t n, float* s_dev,
                            uint32_t* T_dev, void* stream);
 
-/* Copy the counts to the host: int32 [L][2^K] (16-bit counts are widened).  Synchronises
+/* The state a stream of updates keeps (Sec. 3.4.1: the arrays and the point count are all
+ * that Eq. dynadd / dynsub need).  Copy the counts to the host: int32 [L][2^K] (16-bit counts are widened).  Synchronises
  * the device. */
 ace_status ace_get_counts(ace_ctx ctx, int32_t* counts_host);
 
-/* Copy the exact per-table sums to the host: S2 int64 [L], S3 uint64 [L][2] (lo, hi of an
+/* Sec. 3.4.1 running statistics: copy the exact per-table sums to the host: S2 int64 [L], S3 uint64 [L][2] (lo, hi of an
  * unsigned 128-bit integer).  Synchronises the device. */
 ace_status ace_get_table_stats(ace_ctx ctx, int64_t* S2_host, uint64_t* S3_host);
 
-/* Copy the running counters to the host.  Synchronises the device. */
+/* Running counters of the state of Sec. 3.4.1 (n, the scored set) and of the refinement.
+ * Copy them to the host.  Synchronises the device. */
 ace_status ace_get_counters(ace_ctx ctx, ace_counters* out);
 
-/* Restore a saved state: counts int32 [L][2^K] (host) describing n inserted points.  S2 and
+/* Restore a saved state of Sec. 3.4.1: counts int32 [L][2^K] (host) describing n inserted points.  S2 and
  * S3 are recomputed from the counts on the device; the scored set is cleared.  ACE_E_INVALID
  * if a count is negative, a table does not sum to n (with 16-bit counters: a count exceeds
  * 65535 or a table sums to more than n).  Synchronises the device. */
