@@ -574,7 +574,12 @@ def north_star_block(extra):
         ns["connection_log_hash_once"] = {"ms": extra["connection_log_cache_codes"]["ms_per_step"],
                                           "pts_s": extra["connection_log_cache_codes"]["points_per_s"]}
     if "connection_log_counters16" in extra:
-        ns["connection_log_counters16"] = {"ms": extra["connection_log_counters16"]["ms_per_step"]}
+        ns["connection_log_counters16"] = {"ms": extra["connection_log_counters16"]["ms_per_step"],
+                                           "update_ms": extra["connection_log_counters16"]["phase_ms_per_step"]["update_ms"]}
+    if "hot_bucket" in extra:
+        ns["hot_bucket_494021x120"] = {"ms": extra["hot_bucket"]["ms_per_step"],
+                                       "update_ms": extra["hot_bucket"]["phase_ms_per_step"]["update_ms"],
+                                       "score_ms": extra["hot_bucket"]["phase_ms_per_step"]["score_ms"]}
     for key in ("serving_256", "serving_256_graphs"):
         sv = extra.get(key)
         if sv:
@@ -662,7 +667,12 @@ def main():
         c16 = run_workload(Xd, W, K, L, "fp32", steps, warmup, counter_bits=16)
         extra["connection_log_counters16"] = c16
         log(f"  {c16['ms_per_step']:.3f} ms/step, {c16['saturated_increments_last_step']} saturated increments")
-        del Xd
+        log("connection-log shape, every row the same (one hot bucket per table)")
+        Xhot = Xd[:1].expand(n, d).contiguous()
+        extra["hot_bucket"] = run_workload(Xhot, W, K, L, "fp32", steps, warmup)
+        log(f"  {extra['hot_bucket']['ms_per_step']:.3f} ms/step, update "
+            f"{extra['hot_bucket']['phase_ms_per_step']['update_ms']:.4f} ms")
+        del Xd, Xhot
         torch.cuda.empty_cache()
         # the large workloads: at least 10 timed steps after 3 warm-ups (median)
         big_steps, big_warm = max(10, steps // 2), max(3, warmup)

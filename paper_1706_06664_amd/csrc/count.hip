@@ -80,6 +80,22 @@ __device__ inline void add128(u64& lo, u64& hi, u64 alo, u64 ahi) {
 
 constexpr int HIST_THREADS = 1024;
 
+// Wave-level pre-aggregation of equal buckets.  A bucket held by many lanes of a wave (the
+// same code for many rows: duplicated or near-duplicated points) would otherwise take one
+// serialised atomic per lane.  The first active lane names its bucket; if at least 16
+// lanes hold it, that lane takes all of their updates (a scalar test: one compare and one
+// ballot per row, since a fuller search costs more than it saves on ordinary data).
+// Returns how many updates this lane applies to its own bucket: the group's size for the
+// lane that takes it, 0 for the others of the group, 1 for every other lane.
+__device__ inline uint32_t merge_equal_buckets(uint32_t b) {
+    const uint32_t lb = __builtin_amdgcn_readfirstlane(b);
+    const u64 peers = __ballot(b == lb);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    if (cnt < 16 || b != lb) return 1u;
+    const int lane = threadIdx.x & 63;
+    return __builtin_amdgcn_readfirstlane(lane) == lane ? cnt : 0u;
+}
+
 // Move the 16-bit count b (inside its 32-bit word) by delta: saturate at 65535 going up,
 // clamp at 0 (and flag) going down.  Returns the stored value before and after.
 __device__ inline void update16(uint32_t* __restrict__ words, int64_t b, int32_t delta, int32_t& before,
@@ -123,13 +139,27 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
     const int64_t r1 = min(n, r0 + rows_per_block);
     const uint16_t* cj = codes + (int64_t)j * ldc;
     const uint32_t bmask = (uint32_t)(B - 1);  // codes from callers are reduced to K bits
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const uint32_t b = cj[i] & bmask;
+    // Four rows per thread per pass: their codes are loaded before the first merge test,
+    // which needs its row's code in a scalar register.
+    auto add = [&](uint32_t b) {
+        const uint32_t m = merge_equal_buckets(b);
+        if (!m) return;
         if (PACK16)
-            atomicAdd(&hist[b >> 1], 1u << (16 * (b & 1)));
+            atomicAdd(&hist[b >> 1], m << (16 * (b & 1)));
         else
-            atomicAdd(&hist[b], 1u);
+            atomicAdd(&hist[b], m);
+    };
+    const int64_t bd = blockDim.x;
+    int64_t i = r0 + threadIdx.x;
+    for (; i + 3 * bd < r1; i += 4 * bd) {
+        const uint32_t b0 = cj[i] & bmask, b1 = cj[i + bd] & bmask;
+        const uint32_t b2 = cj[i + 2 * bd] & bmask, b3 = cj[i + 3 * bd] & bmask;
+        add(b0);
+        add(b1);
+        add(b2);
+        add(b3);
     }
+    for (; i < r1; i += bd) add(cj[i] & bmask);
     __syncthreads();
     u64 s2 = 0, s3lo = 0, s3hi = 0, dropped = 0;
     for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
@@ -182,7 +212,21 @@ __global__ __launch_bounds__(HIST_THREADS) void update_table_kernel(const uint16
     __syncthreads();
     const uint16_t* cj = codes + (int64_t)j * ldc;
     const uint32_t bmask = (uint32_t)(B - 1);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&hist[cj[i] & bmask], 1u);
+    auto add = [&](uint32_t b) {
+        const uint32_t m = merge_equal_buckets(b);
+        if (m) atomicAdd(&hist[b], m);
+    };
+    const int64_t bd = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + 3 * bd < n; i += 4 * bd) {
+        const uint32_t b0 = cj[i] & bmask, b1 = cj[i + bd] & bmask;
+        const uint32_t b2 = cj[i + 2 * bd] & bmask, b3 = cj[i + 3 * bd] & bmask;
+        add(b0);
+        add(b1);
+        add(b2);
+        add(b3);
+    }
+    for (; i < n; i += bd) add(cj[i] & bmask);
     __syncthreads();
     u64 s2 = 0, s3lo = 0, s3hi = 0, dropped = 0;
     unsigned bad = 0;
@@ -242,19 +286,22 @@ __global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __re
     u64 s2 = 0, s3lo = 0, s3hi = 0;
     if (i < n) {
         const uint32_t b = codes[(int64_t)j * ldc + i] & ((1u << K) - 1u);
-        const int32_t delta = sign > 0 ? 1 : -1;
-        int32_t old, moved;
-        if (C16) {
-            int32_t nv;
-            update16(reinterpret_cast<uint32_t*>(counts_v) + (((int64_t)j << K) >> 1), b, delta, old, nv, err);
-            moved = nv - old;
-            if (sign > 0 && moved == 0) atomicAdd(drops, 1ull);
-        } else {
-            old = atomicAdd(reinterpret_cast<int32_t*>(counts_v) + ((int64_t)j << K) + b, delta);
-            if ((int64_t)old + delta < 0) atomicOr(err, 1u);
-            moved = delta;
+        const uint32_t m = merge_equal_buckets(b);
+        if (m) {
+            const int32_t delta = sign > 0 ? (int32_t)m : -(int32_t)m;
+            int32_t old, moved;
+            if (C16) {
+                int32_t nv;
+                update16(reinterpret_cast<uint32_t*>(counts_v) + (((int64_t)j << K) >> 1), b, delta, old, nv, err);
+                moved = nv - old;
+                if (sign > 0 && moved != delta) atomicAdd(drops, (u64)(delta - moved));
+            } else {
+                old = atomicAdd(reinterpret_cast<int32_t*>(counts_v) + ((int64_t)j << K) + b, delta);
+                if ((int64_t)old + delta < 0) atomicOr(err, 1u);
+                moved = delta;
+            }
+            sq_cube_delta(old, moved, s2, s3lo, s3hi);
         }
-        sq_cube_delta(old, moved, s2, s3lo, s3hi);
     }
     block_sum3(s2, s3lo, s3hi, red);
     if (threadIdx.x == 0) {
