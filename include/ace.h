@@ -52,7 +52,8 @@ typedef enum {
     ACE_E_OVERFLOW = 3,  /* the call would overflow a 32-bit counter or score */
     ACE_E_EMPTY = 4,     /* threshold asked of an empty set */
     ACE_E_DEVICE = 5,    /* a HIP call or kernel failed (sticky) */
-    ACE_E_STATE = 6      /* the call does not fit the context's state (e.g. deleting from an empty bucket) */
+    ACE_E_STATE = 6,     /* the call does not fit the context's state (e.g. deleting from an empty bucket) */
+    ACE_E_TIMEOUT = 7    /* a timed wait ended before the request completed */
 } ace_status;
 
 typedef enum {
@@ -235,6 +236,11 @@ ace_status ace_get_counts(ace_ctx ctx, int32_t* counts_host);
  * unsigned 128-bit integer).  Synchronises the device. */
 ace_status ace_get_table_stats(ace_ctx ctx, int64_t* S2_host, uint64_t* S3_host);
 
+/* Device bytes the context holds (counts, projections, workspace, and the slots of an
+ * attached server): what counts against cfg.mem_budget.  Not a passage of the paper:
+ * admission control for the serving loop. */
+ace_status ace_get_memory(ace_ctx ctx, int64_t* bytes);
+
 /* Running counters of the state of Sec. 3.4.1 (n, the scored set) and of the refinement.
  * Copy them to the host.  Synchronises the device. */
 ace_status ace_get_counters(ace_ctx ctx, ace_counters* out);
@@ -380,10 +386,15 @@ typedef struct {
     int64_t gathered_requests;           /* requests whose rows the gather kernel read */
     double p50_queue_ms, p99_queue_ms;   /* arrival to the launch of the request's batch */
     int64_t graph_launches, graph_captures;
+    int64_t slots;                       /* slots the server holds (fewer than asked under mem_budget) */
+    int64_t cancelled;                   /* requests cancelled before dispatch since the last reset */
 } ace_server_stats;
 
-/* Create a server owning ctx's request stream.  ACE_E_INVALID on a bad config,
- * ACE_E_STATE if ctx already has a server, ACE_E_NOMEM if the slots do not fit. */
+/* Create a server owning ctx's request stream.  Slots are allocated one after another
+ * inside the context's mem_budget: if the budget (or the device) runs out after at least
+ * one slot, the server keeps the slots it has (ace_server_stats.slots) and requests wait in
+ * the queue for one of them, so admission follows the memory there is.  ACE_E_INVALID on a
+ * bad config, ACE_E_STATE if ctx already has a server, ACE_E_NOMEM if not one slot fits. */
 ace_status ace_server_create(ace_ctx ctx, const ace_server_config* cfg, ace_server* out);
 
 /* Admit one request: queue it and return (blocks only while 65,536 requests are pending).
@@ -399,8 +410,27 @@ ace_status ace_server_submit(ace_server srv, int32_t kind, const float* X_host, 
 /* Wait until the request completed; *latency_ms (may be NULL) receives its latency. */
 ace_status ace_server_wait(ace_server srv, uint64_t ticket, double* latency_ms);
 
-/* Wait until every admitted request completed. */
+/* As ace_server_wait, but give up after timeout_ms milliseconds (>= 0): ACE_E_TIMEOUT if
+ * the request has not completed by then (it stays admitted; ace_server_cancel can withdraw
+ * it while it is still queued). */
+ace_status ace_server_wait_for(ace_server srv, uint64_t ticket, double timeout_ms, double* latency_ms);
+
+/* Withdraw a request that is still in the queue (not yet part of a batch): it is never run,
+ * an insert does not count towards the points admitted, and later requests see the state
+ * they would see had it never been submitted (the results equal those of the log without
+ * it).  ACE_OK if it was withdrawn; ACE_E_STATE if it is already in a batch or complete
+ * (then it runs to completion as usual); ACE_E_INVALID for an unknown ticket.  Waiting on a
+ * withdrawn ticket returns ACE_E_STATE at once. */
+ace_status ace_server_cancel(ace_server srv, uint64_t ticket);
+
+/* Wait until every admitted request completed (while a test hold is set, until the hold
+ * is released). */
 ace_status ace_server_drain(ace_server srv);
+
+/* Test hook: with hold = 1 the dispatcher forms no new batch (admitted requests stay in the
+ * queue, where ace_server_cancel and ace_server_wait_for can be exercised deterministically);
+ * hold = 0 resumes.  ace_server_destroy releases a hold. */
+ace_status ace_server_debug_hold(ace_server srv, int32_t hold);
 
 /* Trace-driven load: admit reqs[0..nreq) in order, each at its arrival time (open loop:
  * latency counts from the scheduled arrival, so admission delays are included), with rows

@@ -22,7 +22,7 @@ _MODES = {"scored": THR_SCORED, "const": THR_CONST, "table": THR_TABLE}
 _BOUND = {"measured": 0, "generic": 1}
 
 STATUS = {0: "ACE_OK", 1: "ACE_E_INVALID", 2: "ACE_E_NOMEM", 3: "ACE_E_OVERFLOW", 4: "ACE_E_EMPTY",
-          5: "ACE_E_DEVICE", 6: "ACE_E_STATE"}
+          5: "ACE_E_DEVICE", 6: "ACE_E_STATE", 7: "ACE_E_TIMEOUT"}
 
 # Every symbol include/ace.h declares.
 EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_insert", "ace_delete", "ace_score",
@@ -31,7 +31,8 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_fail_next", "ace_debug_set_capacity", "ace_profile_enable", "ace_get_profile",
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
-           "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe", "ace_hash_static"]
+           "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe", "ace_hash_static", "ace_server_wait_for",
+           "ace_server_cancel", "ace_get_memory", "ace_server_debug_hold"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -90,7 +91,7 @@ class ServerStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("mean_batch_requests", ctypes.c_double),
                 ("gathered_requests", ctypes.c_int64), ("p50_queue_ms", ctypes.c_double),
                 ("p99_queue_ms", ctypes.c_double), ("graph_launches", ctypes.c_int64),
-                ("graph_captures", ctypes.c_int64)]
+                ("graph_captures", ctypes.c_int64), ("slots", ctypes.c_int64), ("cancelled", ctypes.c_int64)]
 
 
 _lib = None
@@ -131,6 +132,10 @@ def load_library(path: str = LIB_PATH):
         "ace_server_create": [P, ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
         "ace_server_submit": [P, i32, P, i64, P, P, i32, ctypes.POINTER(ctypes.c_uint64)],
         "ace_server_wait": [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
+        "ace_server_wait_for": [P, ctypes.c_uint64, f64, ctypes.POINTER(ctypes.c_double)],
+        "ace_server_cancel": [P, ctypes.c_uint64],
+        "ace_server_debug_hold": [P, i32],
+        "ace_get_memory": [P, ctypes.POINTER(ctypes.c_int64)],
         "ace_server_drain": [P],
         "ace_server_replay": [P, P, i64, P, i64, i32, P, P, P],
         "ace_server_get_stats": [P, ctypes.POINTER(ServerStats)],
@@ -324,6 +329,12 @@ class ACE:
         _check(self.lib.ace_get_counters(self.h, ctypes.byref(out)), "ace_get_counters")
         return {f: getattr(out, f) for f, _ in Counters._fields_}
 
+    def memory(self) -> int:
+        """Device bytes the context (and an attached server) holds."""
+        out = ctypes.c_int64()
+        _check(self.lib.ace_get_memory(self.h, ctypes.byref(out)), "ace_get_memory")
+        return out.value
+
     def profile_enable(self, on: bool = True):
         _check(self.lib.ace_profile_enable(self.h, 1 if on else 0), "ace_profile_enable")
 
@@ -431,11 +442,31 @@ class Server:
         self._keep[t.value] = (X, s, T)
         return t.value
 
-    def wait(self, ticket: int) -> float:
+    def wait(self, ticket: int, timeout_ms: Optional[float] = None) -> float:
+        """Latency of the request in ms.  With timeout_ms, raises AceError (ACE_E_TIMEOUT) if
+        it has not completed in time (it stays admitted)."""
         lat = ctypes.c_double()
-        _check(self.lib.ace_server_wait(self.h, int(ticket), ctypes.byref(lat)), "ace_server_wait")
+        if timeout_ms is None:
+            _check(self.lib.ace_server_wait(self.h, int(ticket), ctypes.byref(lat)), "ace_server_wait")
+        else:
+            _check(self.lib.ace_server_wait_for(self.h, int(ticket), float(timeout_ms), ctypes.byref(lat)),
+                   "ace_server_wait_for")
         self._keep.pop(int(ticket), None)
         return lat.value
+
+    def hold(self, on: bool = True):
+        """Test hook: stop (or resume) forming new batches."""
+        _check(self.lib.ace_server_debug_hold(self.h, 1 if on else 0), "ace_server_debug_hold")
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a request still in the queue: True if withdrawn, False if it already
+        runs or ran (it then completes as usual)."""
+        rc = self.lib.ace_server_cancel(self.h, int(ticket))
+        if rc == 6:
+            return False
+        _check(rc, "ace_server_cancel")
+        self._keep.pop(int(ticket), None)
+        return True
 
     def drain(self):
         _check(self.lib.ace_server_drain(self.h), "ace_server_drain")

@@ -348,6 +348,7 @@ const char* ace_status_string(ace_status s) {
         case ACE_E_EMPTY: return "ACE_E_EMPTY";
         case ACE_E_DEVICE: return "ACE_E_DEVICE";
         case ACE_E_STATE: return "ACE_E_STATE";
+        case ACE_E_TIMEOUT: return "ACE_E_TIMEOUT";
         default: return "ACE_E_UNKNOWN";
     }
 }
@@ -877,6 +878,12 @@ ace_status ace_get_table_stats(ace_ctx c, int64_t* S2_host, uint64_t* S3_host) {
     st = check(c, hipMemcpy(S2_host, c->S2, sizeof(u64) * (size_t)c->cfg.L, hipMemcpyDeviceToHost));
     if (st) return st;
     return check(c, hipMemcpy(S3_host, c->S3, sizeof(u64) * 2 * (size_t)c->cfg.L, hipMemcpyDeviceToHost));
+}
+
+ace_status ace_get_memory(ace_ctx c, int64_t* bytes) {
+    if (!c || !bytes) return ACE_E_INVALID;
+    *bytes = (int64_t)c->bytes;
+    return ACE_OK;
 }
 
 ace_status ace_get_counters(ace_ctx c, ace_counters* out) {

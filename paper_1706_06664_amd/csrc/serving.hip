@@ -129,6 +129,7 @@ struct ace_server_s {
     std::mutex submit_mu;            // one submitter at a time
     std::thread dispatcher, completer;
     bool stop = false;
+    bool hold = false;               // test hook: no new batch while set (ace_server_debug_hold)
     ace_status err = ACE_OK;         // first device error (sticky)
     size_t bytes = 0;                // device bytes the slots hold (returned to the budget on destroy)
     std::deque<Req> queue;           // admitted, not yet dispatched
@@ -138,10 +139,11 @@ struct ace_server_s {
     uint64_t ticket_base = 0;        // records start at this ticket
     std::vector<double> latency_ms;  // per ticket since ticket_base (-1 until completed)
     std::vector<double> queue_ms;    // per ticket: arrival to the launch of its batch
-    std::vector<uint8_t> done_of;
+    std::vector<uint8_t> done_of;    // 0 pending, 1 completed, 2 withdrawn (ace_server_cancel)
     std::vector<uint8_t> kind_of;
     std::vector<int64_t> rows_of;
     int64_t batches = 0, batched_requests = 0, gathered_requests = 0, graph_launches = 0, graph_captures = 0;
+    int64_t cancelled = 0;           // requests withdrawn from the queue since the last reset
     int next_slot = 0;
     int last_slot = -1;              // slot of the most recently dispatched batch
     bool have_first = false;
@@ -359,7 +361,7 @@ void dispatch_loop(ace_server srv) {
             std::unique_lock<std::mutex> lk(srv->mu);
             srv->cv.wait(lk, [&] {
                 if (srv->stop && srv->queue.empty()) return true;
-                if (srv->queue.empty()) return false;
+                if (srv->queue.empty() || (srv->hold && !srv->stop)) return false;
                 for (int k = 0; k < S; ++k)
                     if (srv->slots[(srv->next_slot + k) % S].state == SLOT_FREE) return true;
                 return false;
@@ -567,17 +569,25 @@ ace_status ace_server_create(ace_ctx c, const ace_server_config* cfg, ace_server
     srv->slots.resize(cfg->slots);
     const size_t bytes0 = c->bytes;
     ace_status st = ACE_OK;
-    for (auto& sl : srv->slots) {
-        st = alloc_slot(c, sl, cfg->max_rows);
-        if (st) break;
+    int got = 0;
+    for (; got < cfg->slots; ++got) {
+        const size_t before = c->bytes;
+        st = alloc_slot(c, srv->slots[got], cfg->max_rows);
+        if (st) {
+            // give back what the failed slot took; keep the slots that fit
+            free_slot(srv->slots[got]);
+            c->bytes = before;
+            break;
+        }
     }
     srv->bytes = c->bytes - bytes0;
-    if (st) {
+    if (got == 0 || (st && st != ACE_E_NOMEM)) {
         for (auto& sl : srv->slots) free_slot(sl);
-        c->bytes -= srv->bytes;
+        c->bytes = bytes0;
         delete srv;
-        return st;
+        return st ? st : ACE_E_NOMEM;
     }
+    srv->slots.resize(got);
     c->server_attached = 1;
     srv->completer = std::thread(completion_loop, srv);
     srv->dispatcher = std::thread(dispatch_loop, srv);
@@ -591,14 +601,61 @@ ace_status ace_server_submit(ace_server srv, int32_t kind, const float* X_host, 
     return submit_at(srv, kind, X_host, n, s_host, T_host, flags, Clock::now(), ticket);
 }
 
-ace_status ace_server_wait(ace_server srv, uint64_t ticket, double* latency_ms) {
-    if (!srv) return ACE_E_INVALID;
+ace_status ace_server_wait_for(ace_server srv, uint64_t ticket, double timeout_ms, double* latency_ms) {
+    if (!srv || !(timeout_ms >= 0.0)) return ACE_E_INVALID;
     std::unique_lock<std::mutex> lk(srv->mu);
     if (ticket >= srv->next_ticket) return ACE_E_INVALID;
-    srv->cv.wait(lk, [&] { return ticket < srv->ticket_base || srv->done_of[ticket - srv->ticket_base]; });
-    if (latency_ms)
-        *latency_ms = ticket >= srv->ticket_base ? srv->latency_ms[ticket - srv->ticket_base] : -1.0;
+    auto ready = [&] { return ticket < srv->ticket_base || srv->done_of[ticket - srv->ticket_base]; };
+    if (std::isinf(timeout_ms)) {
+        srv->cv.wait(lk, ready);
+    } else {
+        const auto limit = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                              std::chrono::duration<double, std::milli>(timeout_ms));
+        if (!srv->cv.wait_until(lk, limit, ready)) return ACE_E_TIMEOUT;
+    }
+    const bool known = ticket >= srv->ticket_base;
+    if (latency_ms) *latency_ms = known ? srv->latency_ms[ticket - srv->ticket_base] : -1.0;
+    if (known && srv->done_of[ticket - srv->ticket_base] == 2) return ACE_E_STATE;
     return srv->err;
+}
+
+ace_status ace_server_wait(ace_server srv, uint64_t ticket, double* latency_ms) {
+    return ace_server_wait_for(srv, ticket, HUGE_VAL, latency_ms);
+}
+
+ace_status ace_server_debug_hold(ace_server srv, int32_t hold) {
+    if (!srv || (hold != 0 && hold != 1)) return ACE_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->hold = hold != 0;
+    }
+    srv->cv.notify_all();
+    return ACE_OK;
+}
+
+ace_status ace_server_cancel(ace_server srv, uint64_t ticket) {
+    if (!srv) return ACE_E_INVALID;
+    ace_status st = ACE_E_STATE;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (ticket >= srv->next_ticket) return ACE_E_INVALID;
+        for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
+            if (it->ticket != ticket) continue;
+            if (it->kind == ACE_REQ_INSERT) srv->c->n_total -= it->n;
+            if (ticket >= srv->ticket_base) {
+                const size_t i = ticket - srv->ticket_base;
+                srv->done_of[i] = 2;
+                srv->latency_ms[i] = -1.0;
+            }
+            srv->queue.erase(it);
+            --srv->pending;
+            ++srv->cancelled;
+            st = ACE_OK;
+            break;
+        }
+    }
+    if (st == ACE_OK) srv->cv.notify_all();
+    return st;
 }
 
 ace_status ace_server_drain(ace_server srv) {
@@ -684,6 +741,8 @@ ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     s.gathered_requests = srv->gathered_requests;
     s.graph_launches = srv->graph_launches;
     s.graph_captures = srv->graph_captures;
+    s.slots = (int64_t)srv->slots.size();
+    s.cancelled = srv->cancelled;
     s.p50_queue_ms = percentile(qw, 50.0);
     s.p99_queue_ms = percentile(qw, 99.0);
     *out = s;
@@ -701,13 +760,14 @@ ace_status ace_server_reset_stats(ace_server srv) {
     srv->done_of.clear();
     srv->kind_of.clear();
     srv->rows_of.clear();
-    srv->batches = srv->batched_requests = srv->gathered_requests = srv->graph_launches = 0;
+    srv->batches = srv->batched_requests = srv->gathered_requests = srv->graph_launches = srv->cancelled = 0;
     srv->have_first = false;
     return ACE_OK;
 }
 
 ace_status ace_server_destroy(ace_server srv) {
     if (!srv) return ACE_E_INVALID;
+    (void)ace_server_debug_hold(srv, 0);
     (void)ace_server_drain(srv);
     {
         std::lock_guard<std::mutex> lk(srv->mu);

@@ -114,7 +114,7 @@ def test_request_record_layout_matches_header():
     assert [REQUEST_DTYPE.fields[f][1] for f in ("kind", "pad", "n", "row0", "out0", "t_arrival_s")] == \
         [0, 4, 8, 16, 24, 32]
     assert ctypes.sizeof(ServerConfig) == 32
-    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16 + 16
+    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16 + 16 + 16
 
 
 def test_exact_score_rejects_bad_arguments():

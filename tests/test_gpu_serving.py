@@ -258,3 +258,100 @@ def test_serving_bench_configuration(graphs):
         assert abs(th["sigma"] - th_o["sigma"]) <= 1e-12 * max(th_o["sigma"], 1e-300)
     srv.close()
     ace.close()
+
+
+def test_server_slots_follow_memory_budget():
+    """Admission by memory: under a mem_budget that leaves room for 2.5 slots the server keeps
+    2 of the 8 it asks for, requests queue for them, and the results still equal the
+    sequential oracle replay; a budget without room for one slot is refused (ACE_E_NOMEM)."""
+    from paper_1706_06664_amd import ACE, AceError
+    K, L, d = 15, 50, 64
+    kind, n, row0, out0, t, pool = serving_trace(300, d, seed=8, median_batch=32, max_batch=1024)
+    W = projection_matrix(d, K, L, 21)
+    T_o, sk, n_amb = _oracle_replay(kind, n, row0, out0, pool, W, K, L)
+    assert n_amb == 0
+    probe = ACE(W, K, L, max_batch_rows=4096)
+    b_ctx = probe.memory()
+    srv = probe.server(slots=1, max_rows=1024)
+    b_slot = probe.memory() - b_ctx
+    srv.close()
+    assert probe.memory() == b_ctx
+    probe.close()
+    _say(dict(context_bytes=b_ctx, slot_bytes=b_slot))
+    assert b_slot > 0
+    ace = ACE(W, K, L, max_batch_rows=4096, mem_budget=b_ctx + (5 * b_slot) // 2)
+    srv = ace.server(slots=8, max_rows=1024)
+    assert srv.stats()["slots"] == 2
+    assert ace.memory() <= b_ctx + (5 * b_slot) // 2
+    s_out = np.full(T_o.size, -1.0, np.float32)
+    T_out = np.zeros(T_o.size, np.uint32)
+    srv.replay(_records(kind, n, row0, out0, np.zeros_like(t)), pool, s_out, T_out)
+    np.testing.assert_array_equal(T_out.astype(np.int64), T_o)
+    srv.close()
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    ace.close()
+    tight = ACE(W, K, L, max_batch_rows=4096, mem_budget=b_ctx + b_slot // 2)
+    with pytest.raises(AceError) as e:
+        tight.server(slots=2, max_rows=1024)
+    assert e.value.status == 2
+    assert tight.memory() <= b_ctx + b_slot // 2
+    tight.close()
+
+
+def test_server_cancel_and_timed_wait():
+    """Requests withdrawn while still queued never run: the results equal the sequential
+    oracle replay of the log without them.  A timed wait on a queued request ends with
+    ACE_E_TIMEOUT, and waiting on a withdrawn one with ACE_E_STATE.  The test hold keeps the
+    requests queued so that which ones are withdrawn is decided here, not by timing."""
+    from paper_1706_06664_amd import ACE, AceError
+    K, L, d = 15, 50, 64
+    kind, n, row0, out0, t, pool = serving_trace(200, d, seed=9, median_batch=32, max_batch=512)
+    W = projection_matrix(d, K, L, 22)
+    ace = ACE(W, K, L)
+    srv = ace.server(slots=3, max_rows=512, batch_rows=256)
+    srv.hold(True)
+    tickets, outs = [], {}
+    for r in range(len(kind)):
+        X = np.ascontiguousarray(pool[row0[r]:row0[r] + n[r]])
+        if kind[r] == 0:
+            tickets.append(srv.submit("insert", X))
+        else:
+            s = np.full(n[r], -1.0, np.float32)
+            T = np.zeros(n[r], np.uint32)
+            tickets.append(srv.submit("score", X, s, T))
+            outs[r] = (s, T)
+    with pytest.raises(AceError) as e:
+        srv.wait(tickets[5], timeout_ms=20.0)
+    assert e.value.status == 7
+    gone = [r for r in range(len(kind)) if r % 3 == 1]
+    for r in gone:
+        assert srv.cancel(tickets[r])
+    assert not srv.cancel(tickets[gone[0]])   # already withdrawn
+    with pytest.raises(AceError) as e:
+        srv.wait(tickets[gone[0]])
+    assert e.value.status == 6
+    srv.hold(False)
+    srv.drain()
+    st = srv.stats()
+    _say(st)
+    assert st["cancelled"] == len(gone) and st["requests"] == len(kind) - len(gone)
+    assert not srv.cancel(tickets[0])          # completed: nothing to withdraw
+    # the oracle replays the log without the withdrawn requests
+    keep = np.array([r not in set(gone) for r in range(len(kind))])
+    codes, _ = oracle.hash_codes(pool, W, K, L)
+    sk = oracle.Sketch(K, L)
+    for r in range(len(kind)):
+        if not keep[r]:
+            continue
+        c = codes[row0[r]:row0[r] + n[r]]
+        if kind[r] == 0:
+            sk.insert_codes(c)
+        else:
+            T_o = sk.score_codes(c)
+            s, T = outs[r]
+            np.testing.assert_array_equal(T.astype(np.int64), T_o)
+            np.testing.assert_allclose(s, T_o / L, rtol=1e-6, atol=0)
+    srv.close()
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    assert ace.threshold("const", 1.0)["n"] == int(n[keep & (kind == 0)].sum())
+    ace.close()
