@@ -256,3 +256,43 @@ def structured_signs(d: int, K: int, L: int, seed: int):
     B = -(-(K * L) // dp)
     rng = np.random.Generator(np.random.PCG64(seed))
     return (rng.random((B, 3, dp)) < 0.5).astype(np.uint8), dp
+
+
+def serving_rows_torch(n: np.ndarray, d: int, out, seed: int = 5, n_means: int = 8,
+                       drift_per_1000: float = 0.01, anomaly_frac: float = 0.01,
+                       block_rows: int = 1 << 20, device="cuda"):
+    """Rows of a whole request log, written into `out` (float32 [sum n][d], host pinned or
+    device) in request order: request r holds rows [cumsum(n)[r-1], cumsum(n)[r]).  The
+    recipe is drifting_mixture_rows': 8 mixture means ~N(0, 25 I) (the same means and drift
+    signs as drifting_mixture_rows for this seed), mean g shifted by 0.01 (r / 1000) per
+    coordinate along its sign vector, so the drift follows the request id r; unit variance;
+    1% anomalies uniform in [-20, 20]^d.  Rows are drawn on the GPU in blocks of whole
+    requests (about block_rows rows), block b from its own torch Philox stream seeded by
+    (seed, b), so the log is reproducible block by block."""
+    import torch
+    base = np.random.Generator(np.random.PCG64(seed))
+    means = torch.from_numpy(base.standard_normal((n_means, d)) * 5.0).to(device=device, dtype=torch.float32)
+    signs = torch.from_numpy(np.where(base.random((n_means, d)) < 0.5, -1.0, 1.0)).to(device=device,
+                                                                                         dtype=torch.float32)
+    n = np.asarray(n, np.int64)
+    ends = np.cumsum(n)
+    r, row, b = 0, 0, 0
+    while r < len(n):
+        r1 = r
+        while r1 < len(n) and (r1 == r or ends[r1] - row <= block_rows):
+            r1 += 1
+        m = int(ends[r1 - 1] - row)
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed) * 1_000_003 + b)
+        rid = torch.from_numpy(np.repeat(np.arange(r, r1), n[r:r1])).to(device=device, dtype=torch.float32)
+        which = torch.randint(0, n_means, (m,), generator=g, device=device)
+        X = torch.randn((m, d), generator=g, device=device)
+        X += means[which] + (drift_per_1000 * rid / 1000.0)[:, None] * signs[which]
+        anom = torch.rand((m,), generator=g, device=device) < anomaly_frac
+        U = torch.rand((m, d), generator=g, device=device) * 40.0 - 20.0
+        X = torch.where(anom[:, None], U, X)
+        out[row:row + m].copy_(X, non_blocking=False)
+        row += m
+        r = r1
+        b += 1
+    return out

@@ -433,37 +433,68 @@ def heavy_tail_runs(steps, warmup, sample_rows):
     return out
 
 
-def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=False):
-    """Serving workload: d = 256, K = 15, L = 50.  A request log of n_req requests (70%
-    inserts, 30% scores; lognormal sizes, median 256 rows, sigma 1, at most 65,536 rows)
-    replayed against a 262,144-row pinned pool of drifting-mixture rows through the serving
+def serving_log(n_req=100_000, d=256, seed=5):
+    """The serving workload's request log: n_req requests (70% inserts, 30% scores; lognormal
+    sizes, median 256 rows, sigma 1, clipped to 1..65,536; Poisson arrivals), every request
+    with rows of its own in request order, the mixture means drifting with the request id.
+    The rows (about 43 GB for 100,000 requests) are drawn on the GPU and kept in pinned host
+    memory (pageable if pinning fails): serving reads them over the host link."""
+    import numpy as np
+    import torch
+    from ace_inputs import serving_requests, serving_rows_torch
+    from paper_1706_06664_amd import REQUEST_DTYPE
+    reqs = serving_requests(n_req, seed=seed)
+    kind = np.array([0 if q.kind == "insert" else 1 for q in reqs], np.int32)
+    n = np.array([q.n for q in reqs], np.int64)
+    t = np.array([q.arrival_s for q in reqs], np.float64)
+    rows = int(n.sum())
+    t0 = time.perf_counter()
+    try:
+        pool = torch.empty((rows, d), dtype=torch.float32, pin_memory=True)
+        pinned = True
+    except RuntimeError:
+        pool = torch.empty((rows, d), dtype=torch.float32)
+        pinned = False
+    serving_rows_torch(n, d, pool, seed=seed, device="cuda:0")
+    torch.cuda.synchronize()
+    log(f"serving log: {n_req} requests, {rows} rows ({rows * d * 4 / 1e9:.1f} GB, "
+        f"{'pinned' if pinned else 'pageable'}) drawn in {time.perf_counter() - t0:.1f} s")
+    rec = np.zeros(n_req, REQUEST_DTYPE)
+    sc = kind == 1
+    out0 = np.zeros(n_req, np.int64)
+    out0[sc] = np.concatenate([[0], np.cumsum(n[sc])[:-1]])
+    rec["kind"], rec["n"], rec["row0"], rec["out0"] = kind, n, np.concatenate([[0], np.cumsum(n)[:-1]]), out0
+    return {"rec": rec, "t": t, "pool": pool, "pinned": pinned, "rows": rows, "scored": int(n[sc].sum()),
+            "n_req": n_req, "d": d}
+
+
+def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=False):
+    """Serving workload: d = 256, K = 15, L = 50, the whole request log through the serving
     loop.  Closed loop (every request queued at once) gives the saturation rate in FP32 and
     BF16; open loop (Poisson arrivals at 0.5, 0.8 and 0.95 of the BF16 saturation request
     rate) gives latency percentiles, from arrival to completion (host copies included)."""
     import numpy as np
     import torch
-    from ace_inputs import projection_matrix, serving_trace
-    from paper_1706_06664_amd import ACE, REQUEST_DTYPE
-    K, L, d = 15, 50, 256
-    kind, n, row0, out0, t, pool = serving_trace(n_req, d, seed=5, pool_rows=262_144)
+    from ace_inputs import projection_matrix
+    from paper_1706_06664_amd import ACE
+    K, L, d = 15, 50, lg["d"]
     W = projection_matrix(d, K, L, 1706066645)
-    poolp = torch.from_numpy(pool).pin_memory()
-    m = int(n[kind == 1].sum())
-    s_out = torch.zeros(m, dtype=torch.float32).pin_memory()
-    T_out = torch.zeros(m, dtype=torch.int32).pin_memory()
-    rec = np.zeros(n_req, REQUEST_DTYPE)
-    rec["kind"], rec["n"], rec["row0"], rec["out0"] = kind, n, row0, out0
+    rec, t, pool, n_req = lg["rec"], lg["t"], lg["pool"], lg["n_req"]
+    s_out = torch.zeros(lg["scored"], dtype=torch.float32, pin_memory=lg["pinned"])
+    T_out = torch.zeros(lg["scored"], dtype=torch.int32, pin_memory=lg["pinned"])
 
     def run(prec, arr=None):
         ace = ACE(W, K, L, precision=prec)
         srv = ace.server(slots=slots, max_rows=65_536, gather_max_bytes=gather_max_bytes, batch_rows=batch_rows,
                          graphs=graphs)
-        srv.replay(rec[:500], poolp, s_out, T_out, pinned=True)   # warm-up
+        srv.replay(rec[:500], pool, s_out, T_out, pinned=lg["pinned"])   # warm-up
+        ace.reset()
+        torch.cuda.synchronize()
         srv.reset_stats()
         r = rec.copy()
         if arr is not None:
             r["t_arrival_s"] = arr
-        srv.replay(r, poolp, s_out, T_out, pinned=True)
+        srv.replay(r, pool, s_out, T_out, pinned=lg["pinned"])
         st = srv.stats()
         srv.close()
         ace.close()
@@ -473,24 +504,24 @@ def serving_runs(n_req=20_000, slots=8, batch_rows=4096, gather_max_bytes=65536,
                 "max_ms": st["max_ms"], "batches": st["batches"],
                 "mean_batch_requests": st["mean_batch_requests"], "graph_launches": st["graph_launches"]}
 
-    out = {"workload": f"serving d={d}, K={K}, L={L}: {n_req} requests, {int(n.sum())} rows, 70% inserts, "
-                       f"lognormal sizes (median 256, sigma 1)",
+    out = {"workload": f"serving d={d}, K={K}, L={L}: {n_req} requests, {lg['rows']} rows, 70% inserts, "
+                       f"lognormal sizes (median 256, sigma 1), drift by request id",
            "server": {"slots": slots, "batch_rows": batch_rows, "gather_max_bytes": gather_max_bytes,
-                      "max_rows": 65_536, "graphs": graphs}}
+                      "max_rows": 65_536, "graphs": graphs, "pinned_rows": lg["pinned"]}}
     for prec in ("fp32", "bf16"):
-        log(f"serving closed loop {prec}")
+        log(f"serving closed loop {prec}{' (graphs)' if graphs else ''}")
         out[f"closed_loop_{prec}"] = run(prec)
         log(f"  {out[f'closed_loop_{prec}']['points_per_s']:.3e} points/s")
     sat = out["closed_loop_bf16"]["requests_per_s"]
     out["open_loop_bf16"] = []
     base_rate = n_req / t[-1]
     for load in (0.5, 0.8, 0.95):
-        log(f"serving open loop bf16 at {load} of saturation")
+        log(f"serving open loop bf16 at {load} of saturation{' (graphs)' if graphs else ''}")
         o = run("bf16", arr=t * (base_rate / (load * sat)))
         o["load"] = load
         o["offered_requests_per_s"] = load * sat
         out["open_loop_bf16"].append(o)
-        log(f"  p50 {o['p50_ms']:.3f} ms, p99 {o['p99_ms']:.3f} ms")
+        log(f"  p50 {o['p50_ms']:.3f} ms, p99 {o['p99_ms']:.3f} ms, {o['points_per_s']:.3e} points/s")
     out["bf16_vs_fp32_closed_loop"] = out["closed_loop_bf16"]["points_per_s"] / out["closed_loop_fp32"]["points_per_s"]
     out["pcie_bound_points_per_s"] = 55e9 / (4 * d)
     return out
@@ -587,7 +618,8 @@ def north_star_block(extra):
                                         "bf16": sv["closed_loop_bf16"]["points_per_s"]},
                        "open_bf16": [{"load": o["load"], "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
                                       "pts_s": o["points_per_s"]} for o in sv["open_loop_bf16"]],
-                       "requests": sv["workload"].split(": ")[1].split(",")[0]}
+                       "requests": sv["workload"].split(": ")[1].split(",")[0],
+                       "rows": sv["workload"].split(": ")[1].split(", ")[1]}
     ex = extra.get("exact_score_connection_log")
     if ex:
         ns["exact_S"] = {"ms": ex["ms_per_launch"], "fp64_mfma_frac": ex["roofline"]["frac"]}
@@ -605,6 +637,7 @@ def main():
     ap.add_argument("--sample-rows", type=int, default=65_536,
                     help="rows of the low-rank and heavy-tail workloads the oracle hashes")
     ap.add_argument("--detail", default=None, help="write every record to this JSON file")
+    ap.add_argument("--serving-requests", type=int, default=100_000)
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--traffic-run", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration), then two headline inserts "
@@ -678,9 +711,11 @@ def main():
         big_steps, big_warm = max(10, steps // 2), max(3, warmup)
         extra["low_rank_1024"] = low_rank_runs(args.low_rank_n, big_steps, big_warm, args.sample_rows)
         extra["heavy_tail_4096"] = heavy_tail_runs(big_steps, big_warm, args.sample_rows)
-        extra["serving_256"] = serving_runs()
-        log("serving with captured graphs")
-        extra["serving_256_graphs"] = serving_runs(graphs=True)
+        lg = serving_log(args.serving_requests)
+        extra["serving_256"] = serving_runs(lg)
+        extra["serving_256_graphs"] = serving_runs(lg, graphs=True)
+        del lg
+        torch.cuda.empty_cache()
         log("exact S(q, D) and estimator study")
         extra["exact_score_connection_log"] = exact_score_runs(X, W, K)
         log(f"  {extra['exact_score_connection_log']['ms_per_launch']:.3f} ms per launch")
