@@ -669,10 +669,8 @@ ace_status ace_reset(ace_ctx c, void* stream) {
     Bracket br(c, s, CLS_OTHER);
     const size_t cb = (size_t)(c->cbits / 8) * (size_t)c->cfg.L << c->cfg.K;
     st = check(c, launch_zero(c->counts, cb, s));
-    if (!st) st = check(c, launch_zero(c->rcnt + 3, sizeof(u64), s));
-    if (!st) st = check(c, launch_zero(c->S2, sizeof(u64) * (size_t)c->cfg.L, s));
-    if (!st) st = check(c, launch_zero(c->S3, sizeof(u64) * 2 * (size_t)c->cfg.L, s));
-    if (!st) st = check(c, launch_zero(c->mom, sizeof(u64) * 4, s));
+    if (!st)
+        st = check(c, launch_zero_small(c->rcnt + 3, 1, c->S2, c->cfg.L, c->S3, 2 * (int64_t)c->cfg.L, c->mom, 4, s));
     if (!st) c->n_total = 0;
     return st;
 }

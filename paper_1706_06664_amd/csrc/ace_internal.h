@@ -149,6 +149,10 @@ hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, cons
 hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);
 hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L, u64* S2, u64* S3, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Zero up to four small ranges of 64-bit words (each < 2^31 words; a null pointer with 0
+// words is skipped) in one launch.
+hipError_t launch_zero_small(u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2, int64_t w2, u64* p3, int64_t w3,
+                             hipStream_t s);
 // S[q] = sum_x p(q, x)^K (and S2[q] = sum_x p(q, x)^{2K} when S2 != nullptr); m >= 1.
 hipError_t launch_exact_score(const float* Q, int64_t m, const float* X, int64_t n, int d, int K, double* S,
                               double* S2, hipStream_t s);

@@ -364,9 +364,30 @@ __device__ inline double u128_to_double(u64 lo, u64 hi) {
     return ldexp((double)(top | (rest != 0 ? 1ull : 0ull)), 64 - sh);
 }
 
-__global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, const u64* __restrict__ S3,
-                                 const u64* __restrict__ mom, int mode, double alpha, DevThresh* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block: thread j takes tables j, j + blockDim, ... (the sum of S2 in 128 bits and the
+// per-table deviations), block sums, then thread 0 finishes in FP64.
+__global__ __launch_bounds__(256) void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2,
+                                                        const u64* __restrict__ S3, const u64* __restrict__ mom,
+                                                        int mode, double alpha, DevThresh* __restrict__ out) {
+    __shared__ u64 red[3 * 4];
+    __shared__ double dsum[4];
+    u64 s2lo = 0, s2hi = 0, unused = 0;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        add128(s2lo, s2hi, S2[j], 0ull);
+        if (n > 0) {
+            const u128 s3 = ((u128)S3[2 * j + 1] << 64) | S3[2 * j];
+            const i128 s2 = (i128)(int64_t)S2[j];
+            const i128 v = (i128)n * (i128)s3 - s2 * s2;
+            const u128 uv = (u128)v;
+            acc += sqrt(u128_to_double((u64)uv, (u64)(uv >> 64))) / (double)n;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) dsum[threadIdx.x >> 6] = acc;
+    block_sum3(unused, s2lo, s2hi, red);
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) acc += dsum[w];
     DevThresh r;
     r.n = n;
     r.m_scored = (int64_t)mom[0];
@@ -374,9 +395,7 @@ __global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, c
     r.status = 0;
     // sum_j S2_j reaches 2^63 well inside the INT32_MAX insert cap (L tables of n^2 each):
     // it is summed and converted in 128 bits.
-    u128 s2tot = 0;
-    for (int j = 0; j < L; ++j) s2tot += (u128)S2[j];
-    r.mu = n > 0 ? u128_to_double((u64)s2tot, (u64)(s2tot >> 64)) / ((double)n * (double)L) : 0.0;
+    r.mu = n > 0 ? u128_to_double(s2lo, s2hi) / ((double)n * (double)L) : 0.0;
     const int64_t m = (int64_t)mom[0];
     const int64_t sumT = (int64_t)mom[1];
     r.mu_scored = 0.0;
@@ -388,18 +407,7 @@ __global__ void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2, c
         r.mu_scored = (double)sumT / ((double)m * (double)L);
         r.sigma = sqrt(u128_to_double((u64)un, (u64)(un >> 64))) / ((double)m * (double)L);
     }
-    r.sigma_table = 0.0;
-    if (n > 0) {
-        double acc = 0.0;
-        for (int j = 0; j < L; ++j) {
-            const u128 s3 = ((u128)S3[2 * j + 1] << 64) | S3[2 * j];
-            const i128 s2 = (i128)(int64_t)S2[j];
-            const i128 v = (i128)n * (i128)s3 - s2 * s2;
-            const u128 uv = (u128)v;
-            acc += sqrt(u128_to_double((u64)uv, (u64)(uv >> 64))) / (double)n;
-        }
-        r.sigma_table = acc / (double)L;
-    }
+    r.sigma_table = n > 0 ? acc / (double)L : 0.0;
     r.tau = 0.0;
     if (mode == ACE_THR_SCORED) {
         if (m == 0) r.status = ACE_E_EMPTY;
@@ -447,6 +455,18 @@ __global__ __launch_bounds__(256) void table_sums_kernel(const CT* __restrict__ 
 __global__ __launch_bounds__(256) void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
+}
+
+struct ZeroRanges {
+    u64* p[4];
+    int32_t words[4];   // 64-bit words each
+};
+
+// Several small ranges of 64-bit words in one launch (one block; ranges of a few KB).
+__global__ __launch_bounds__(256) void zero_ranges_kernel(const ZeroRanges r) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int i = threadIdx.x; i < r.words[k]; i += blockDim.x) r.p[k][i] = 0ull;
 }
 
 }  // namespace
@@ -539,7 +559,7 @@ hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, in
 
 hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode, double alpha,
                             DevThresh* out, hipStream_t s) {
-    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(64), 0, s, n, L, S2, S3, mom, mode, alpha, out);
+    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(256), 0, s, n, L, S2, S3, mom, mode, alpha, out);
     return hipGetLastError();
 }
 
@@ -558,6 +578,13 @@ hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L,
     else
         hipLaunchKernelGGL(table_sums_kernel<int32_t>, dim3((unsigned)L), dim3(256), 0, s,
                            reinterpret_cast<const int32_t*>(counts), K, S2, S3);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_small(u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2, int64_t w2, u64* p3, int64_t w3,
+                             hipStream_t s) {
+    ZeroRanges r{{p0, p1, p2, p3}, {(int32_t)w0, (int32_t)w1, (int32_t)w2, (int32_t)w3}};
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3(1), dim3(256), 0, s, r);
     return hipGetLastError();
 }
 
