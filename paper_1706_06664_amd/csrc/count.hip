@@ -352,7 +352,53 @@ __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__
     }
 }
 
-// Threshold statistics from the exact sums (one thread).
+// Query phase for large batches, table by table: thread g holds rows g and g + G (G threads
+// in all) and walks the tables in order, gathering both rows' counts from table j before it
+// moves to table j + 1.  Every workgroup then stays near the same table, so the counts it
+// gathers are mostly in the L2 of its XCD (connection-log, 6.55 MB of counts: 0.113 against
+// 0.130 ms for one row per thread with four tables per step).  Grid: ceil(n / 2) threads.
+template <typename CT>
+__global__ __launch_bounds__(256) void score_tables_kernel(const uint16_t* __restrict__ codes, int64_t ldc, int64_t n,
+                                                           int K, int L, const CT* __restrict__ counts,
+                                                           float* __restrict__ s_out, uint32_t* __restrict__ T_out,
+                                                           u64* __restrict__ mom) {
+    __shared__ u64 red[3 * 4];
+    const int64_t G = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, i1 = i0 + G;
+    const bool ok0 = i0 < n, ok1 = i1 < n;
+    const uint32_t bm = (1u << K) - 1u;  // codes from callers are reduced to K bits
+    uint32_t T0 = 0, T1 = 0;
+    for (int j = 0; j < L; ++j) {
+        const uint16_t* cj = codes + (int64_t)j * ldc;
+        const CT* aj = counts + ((int64_t)j << K);
+        const uint32_t b0 = ok0 ? (cj[i0] & bm) : 0u, b1 = ok1 ? (cj[i1] & bm) : 0u;
+        if (ok0) T0 += (uint32_t)aj[b0];
+        if (ok1) T1 += (uint32_t)aj[b1];
+    }
+    u64 sT = 0, lo = 0, hi = 0;
+    if (ok0) {
+        if (s_out) s_out[i0] = (float)((double)T0 / (double)L);
+        if (T_out) T_out[i0] = T0;
+        sT += T0;
+        const u128 t2 = (u128)T0 * (u128)T0;
+        add128(lo, hi, (u64)t2, (u64)(t2 >> 64));
+    }
+    if (ok1) {
+        if (s_out) s_out[i1] = (float)((double)T1 / (double)L);
+        if (T_out) T_out[i1] = T1;
+        sT += T1;
+        const u128 t2 = (u128)T1 * (u128)T1;
+        add128(lo, hi, (u64)t2, (u64)(t2 >> 64));
+    }
+    block_sum3(sT, lo, hi, red);
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) atomicAdd(&mom[0], (u64)n);
+        atomicAdd(&mom[1], sT);
+        atomic_add_u128(&mom[2], lo, hi);
+    }
+}
+
+// Threshold statistics from the exact sums.
 // Unsigned 128-bit integer to the nearest double (ties to even): the top 64 significant
 // bits, with a sticky bit for anything below them, go through the correctly rounded u64
 // conversion (the sticky bit sits below the rounding position), then an exact scaling.
@@ -547,6 +593,16 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
 hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
                         int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (n >= 131072) {   // at least 256 workgroups of the table-by-table kernel
+        const unsigned blocks = (unsigned)(((n + 1) / 2 + 255) / 256);
+        if (counter_bits == 16)
+            hipLaunchKernelGGL(score_tables_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, codes, ldc, n, K, L,
+                               reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom);
+        else
+            hipLaunchKernelGGL(score_tables_kernel<int32_t>, dim3(blocks), dim3(256), 0, s, codes, ldc, n, K, L,
+                               reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom);
+        return hipGetLastError();
+    }
     const int64_t nb = (n + 255) / 256;
     if (counter_bits == 16)
         hipLaunchKernelGGL(score_kernel<uint16_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,

@@ -264,3 +264,33 @@ def test_refine_queue_full_path(precision):
     assert np.array_equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1] and res[0][1] >= 64 * K * L
     assert np.array_equal(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("bits", [32, 16])
+@pytest.mark.parametrize("n", [131_071, 131_072, 200_003])
+def test_score_large_batches_from_codes(bits, n):
+    """Scoring batches of 131,072 rows or more takes the table-by-table kernel (two rows per
+    thread).  Codes with hot buckets (a quarter of the rows share one code per table) are
+    inserted and scored through ace_insert_codes / ace_score_codes and compared with the
+    oracle: every T, s, the counts and the scored-set statistics; odd n leaves the last
+    thread's second row out."""
+    import torch
+    from paper_1706_06664_amd import ACE
+    from tests.parity import check_thresh
+    K, L = 13, 37
+    rng = np.random.default_rng(n + bits)
+    codes = rng.integers(0, 1 << K, size=(n, L), dtype=np.int64).astype(np.uint16)
+    codes[: n // 4] = codes[0]
+    sk = oracle.Sketch(K, L, cap=65535 if bits == 16 else None)
+    sk.insert_codes(codes)
+    T_o = sk.score_codes(codes)
+    _, th_o = sk.threshold(oracle.MODE_SCORED, 1.0)
+    ace = ACE(projection_matrix(8, K, L, 5), K, L, counter_bits=bits)
+    cd = torch.from_numpy(codes.T.copy().view(np.int16)).to("cuda:0")
+    ace.insert_codes(cd)
+    s, T = ace.score_codes(cd)
+    np.testing.assert_array_equal(T.cpu().numpy().astype(np.int64), T_o)
+    np.testing.assert_allclose(s.cpu().numpy(), T_o / L, rtol=1e-6, atol=0)
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    check_thresh(ace.threshold("scored", 1.0), th_o)
+    ace.close()
