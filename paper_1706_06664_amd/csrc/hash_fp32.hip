@@ -66,9 +66,13 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
                                      const float (&wcol)[TW], int64_t rbase, int cbase, int64_t nv, int lane,
                                      uint32_t tmask = ~0u) {
     const int kin = lane >> 4, cl = lane & 15;
-    uint32_t rok = 0;
+    // Rows past the batch's real rows take no bits (only the last row tile has any).
+    uint32_t rok = 4 * RB >= 32 ? 0xFFFFFFFFu : (1u << (4 * RB)) - 1u;
+    if (rbase + 16 * RB > nv) {
+        rok = 0;
 #pragma unroll
-    for (int e = 0; e < 4 * RB; ++e) rok |= (rbase + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+        for (int e = 0; e < 4 * RB; ++e) rok |= (rbase + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+    }
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = rbase + lane;  // the row whose codes this lane stores (lanes < 16 RB)
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
@@ -293,9 +297,10 @@ __global__ __launch_bounds__(256) void hash_fp32_kernel(const HashArgs a) {
 // Tiling: 4 waves as 2 (rows) x 2 (columns); a wave holds RB 16-row blocks x TW tables.
 //
 // Row norm: each lane sums the squares of its k values in FP32 (one rounding per fused
-// multiply-add, at most d/4 + 3 of them); the four k groups are added in FP64.  The sum is
-// scaled by norm_up = 1 + (DP + 2) 2^-23 >= 1 + gamma_{d/4+3}(2^-24), and (d + 16) 2^-125
-// is added for squares lost below the normal range: an upper bound of ||x||^2.
+// multiply-add, at most d/4 + 3 of them); the four k groups are added in FP32 (two more).
+// The sum is scaled by norm_up = 1 + (DP + 2) 2^-23 >= 1 + gamma_{d/4+5}(2^-24), and
+// (d + 16) 2^-125 is added for squares lost below the normal range: an upper bound of
+// ||x||^2.
 template <int TW, int RB, int REM, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVES, DIRECT_WAVES))) void hash_fp32_direct_kernel(
     const HashArgs a, int64_t tiles_m, int64_t n_slots) {
@@ -525,10 +530,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         float rbnd[4 * RB];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            double s2 = (double)ss[b];
+            // The four k groups' sums are added in FP32 (two more roundings: d/4 + 5 in all,
+            // well inside norm_up), then the root and products are taken in FP32: their few
+            // roundings are covered by the 2^-20 margin.
+            float s2 = ss[b];
             s2 += __shfl_xor(s2, 16, 64);
             s2 += __shfl_xor(s2, 32, 64);
-            const float rb = (float)(gx * sqrt(s2 * (double)a.norm_up + (double)(d + 16) * 0x1p-125) * (1.0 + 0x1p-20));
+            const float rb = gx * sqrtf(fmaf(s2, a.norm_up, (float)(d + 16) * 0x1p-125f)) * (1.f + 0x1p-20f);
 #pragma unroll
             for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = __shfl(rb, 4 * kin + r, 64);
         }
