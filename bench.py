@@ -411,6 +411,25 @@ def heavy_tail_runs(steps, warmup, sample_rows):
     del c32, c8
     Xs = X4[:sample_rows].contiguous()
     codes = {m: sample_codes((W4, K4, L4, {"precision": m}), Xs) for m in ("fp32", "bf16")}
+    # e4m3 before and after refinement on the sample: raw signs, and the FP64 pass over every
+    # bit inside the e4m3 bound (almost all of them on this data), timed
+    codes["fp8_raw"] = sample_codes((W4, K4, L4, {"precision": "fp8", "refine": 0}), Xs)
+    a8 = ACE(W4, K4, L4, precision="fp8", refine=1)
+    a8.hash(Xs)
+    torch.cuda.synchronize()
+    c0 = a8.counters()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    c8 = a8.hash(Xs)
+    e1.record()
+    torch.cuda.synchronize()
+    c1 = a8.counters()
+    from paper_1706_06664_amd import codes_as_uint16
+    codes["fp8_refined"] = codes_as_uint16(c8)
+    out["fp8_refined_sample"] = {"rows": sample_rows, "hash_ms": e0.elapsed_time(e1),
+                                 "refined_frac": (c1["bits_refined"] - c0["bits_refined"]) /
+                                                 max(1, c1["bits_hashed"] - c0["bits_hashed"])}
+    a8.close()
     log(f"heavy-tail oracle sample: {sample_rows} rows")
     out["oracle_sample"] = oracle_sample_check(X4, W4, K4, L4, codes, sample_rows)
     log(f"  {out['oracle_sample']}")
@@ -592,6 +611,11 @@ def north_star_block(extra):
     if ht:
         ns["heavy_tail_1000000x4096"] = {
             "bf16_vs_fp32": ht["bf16_speedup"], "fp32": brief(ht["fp32"]), "bf16": brief(ht["bf16"]),
+            "e4m3_refined_sample": {"rows": ht["fp8_refined_sample"]["rows"],
+                                    "hash_ms": ht["fp8_refined_sample"]["hash_ms"],
+                                    "refined": ht["fp8_refined_sample"]["refined_frac"],
+                                    "raw_flips": ht["oracle_sample"]["fp8_raw_unrefined_flips"],
+                                    "flips_after": ht["oracle_sample"]["fp8_refined_unrefined_flips"]},
             "e4m3_raw": {"ms": ht["fp8"]["ms_per_step"], "vs_fp32": ht["fp8_raw_speedup"],
                          "proj_frac": ht["fp8"]["roofline"]["frac"], "flip_rate": ht["fp8_raw_flip_rate"],
                          "score_err_mean": ht["fp8_raw_score_error"]["mean_rel"],
