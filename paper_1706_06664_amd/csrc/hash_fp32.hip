@@ -26,6 +26,8 @@
 // rows x TW tables = 4 x TW MFMA tiles of 16x16.  The contraction runs in chunks of 32
 // through LDS; both operands are stored k-contiguous so each lane reads one float4 per
 // 16-wide k block and feeds four MFMAs with it.
+#include <type_traits>
+
 #include "ace_internal.h"
 
 namespace ace {
@@ -41,12 +43,21 @@ constexpr int DIRECT_WAVES = 2;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane) {
-    // Lane l wants row rho = l & 15 of a 16-row tile; that row's 16 bits sit in ballot
-    // r = rho & 3, bit field g = rho >> 2 (lane 16g + c holds column c of row 4g + r).
-    const int r = lane & 3, g = (lane & 15) >> 2;
-    u64 m = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
-    return (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+// Sign packing.  Lane l stores row rho = l & 15 of 16-row tile l >> 4.  Tile b's ballot of
+// accumulator element r holds row 4g + r in bits 16g .. 16g + 15 (lane 16g + c holds column
+// c), so lane l needs ballot pick = 4 (l >> 4) + (l & 3) shifted right by 16 ((l & 15) >> 2).
+// f[e] is ballot e already shifted by the lane's amount; a select tree over the bits of pick
+// keeps the lane's own (masks, not branches or a switch).  Lanes with pick >= N get an unused
+// value.
+template <int N>
+__device__ inline uint32_t pick_code(uint32_t (&f)[N], int pick) {
+#pragma unroll
+    for (int w = 1; w < N; w <<= 1) {
+        const uint32_t m = 0u - (uint32_t)((pick & w) != 0);
+#pragma unroll
+        for (int i = 0; i + w < N; i += 2 * w) f[i] = (f[i + w] & m) | (f[i] & ~m);
+    }
+    return f[0];
 }
 
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
@@ -66,15 +77,23 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
                                      const float (&wcol)[TW], int64_t rbase, int cbase, int64_t nv, int lane,
                                      uint32_t tmask = ~0u) {
     const int kin = lane >> 4, cl = lane & 15;
-    // Rows past the batch's real rows take no bits (only the last row tile has any).
-    uint32_t rok = 4 * RB >= 32 ? 0xFFFFFFFFu : (1u << (4 * RB)) - 1u;
+    // Rows past the batch's real rows (only the last row tile has any) take no bits: their
+    // accumulators become +inf, outside every bound, and their codes are not stored.
     if (rbase + 16 * RB > nv) {
-        rok = 0;
 #pragma unroll
-        for (int e = 0; e < 4 * RB; ++e) rok |= (rbase + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+        for (int e = 0; e < 4 * RB; ++e)
+            if (rbase + 16 * (e >> 2) + 4 * kin + (e & 3) >= nv) {
+#pragma unroll
+                for (int t = 0; t < TW; ++t) acc[e >> 2][t][e & 3] = __builtin_inff();
+            }
     }
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = rbase + lane;  // the row whose codes this lane stores (lanes < 16 RB)
+    const int pick = 4 * kin + (lane & 3), sh = 16 * ((lane & 15) >> 2);
+    // The largest of this lane's row bound factors (the maximum keeps a NaN).
+    float rbmax = rbnd[0];
+#pragma unroll
+    for (int e = 1; e < 4 * RB; ++e) rbmax = __builtin_elementwise_maximum(rbmax, rbnd[e]);
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
@@ -82,29 +101,48 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
         const int table = (cbase >> 4) + t;
         const int cp = cbase + t * 16 + cl;
         const float wbv = wcol[t];
-        // Bit e of umask: accumulator element e lies inside its bound.
-        uint32_t umask = 0;
         const bool chk = a.refine && wbv >= 0.f;
+        // Is any accumulator element of this lane inside its bound?  (NaN is uncertain too.)
+        // First against the lane's largest bound (one comparison of the smallest |acc|; the
+        // minimum keeps a NaN), then, only where that fails somewhere in the wave, element by
+        // element.
+        float amin = fabsf(acc[0][t][0]);
 #pragma unroll
-        for (int e = 0; e < 4 * RB; ++e) {
-            const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
-            umask |= (chk && !(fabsf(acc[e >> 2][t][e & 3]) > thr)) ? (1u << e) : 0u;  // NaN is uncertain too
-        }
-        umask &= rok;
-        if (a.refine == 2) {
-            n_unc += __popc(umask);  // count only: the raw signs stand
-            umask = 0;
+        for (int e = 1; e < 4 * RB; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(acc[e >> 2][t][e & 3]));
+        const bool maybe = chk && !(amin > fmaf(rbmax, wbv, a.eps_abs));
+        bool unc = false;
+        if (__any(maybe)) {
+            // (The empty asm keeps these 4 RB bounds from being computed ahead of the test.)
+            float wv = wbv;
+            asm volatile("" : "+v"(wv));
+#pragma unroll
+            for (int e = 0; e < 4 * RB; ++e) unc |= !(fabsf(acc[e >> 2][t][e & 3]) > fmaf(rbnd[e], wv, a.eps_abs));
+            unc = unc && chk;
         }
         uint32_t code = 0;
-        if (!__any(umask != 0)) {
+        if (a.refine != 2 && !__any(unc)) {
             // Common case: the signs stand; ballots straight from the accumulators.
+            uint32_t f[4 * RB];
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
-                                                __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
-                code = (kin == b) ? cb : code;
+            for (int e = 0; e < 4 * RB; ++e) {
+                f[e] = (uint32_t)(__ballot(acc[e >> 2][t][e & 3] > 0.f) >> sh);
+                // Shift each ballot as it is taken: selecting the unshifted scalar pairs
+                // first would cost two vector selects (and copies) per pair.
+                asm("" : "+v"(f[e]));
             }
+            code = pick_code(f, pick);
         } else {
+            // Bit e of umask: accumulator element e lies inside its bound.
+            uint32_t umask = 0;
+#pragma unroll
+            for (int e = 0; e < 4 * RB; ++e) {
+                const float thr = fmaf(rbnd[e], wbv, a.eps_abs);
+                umask |= (chk && !(fabsf(acc[e >> 2][t][e & 3]) > thr)) ? (1u << e) : 0u;
+            }
+            if (a.refine == 2) {
+                n_unc += __popc(umask);  // count only: the raw signs stand
+                umask = 0;
+            }
             // Rare: queue each uncertain (row, column) for the FP64 pass, one atomic per wave;
             // bit e of pos is the sign of element e (patched where decided in place).
             uint32_t pos = 0;
@@ -119,8 +157,10 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
             }
             const uint32_t total = __shfl(incl, 63, 64);
             u64 base = 0;
-            if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
-            base = __shfl(base, 0, 64);
+            if (total != 0) {
+                if (lane == 0) base = atomicAdd(a.list_count, (u64)total);
+                base = __shfl(base, 0, 64);
+            }
             u64 slot = base + (incl - mine);
             uint32_t todo = umask;
             while (todo) {
@@ -143,13 +183,10 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
                 }
                 ++slot;
             }
+            uint32_t f[4 * RB];
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const uint32_t cb = select_code(__ballot((pos >> (4 * b)) & 1u), __ballot((pos >> (4 * b + 1)) & 1u),
-                                                __ballot((pos >> (4 * b + 2)) & 1u), __ballot((pos >> (4 * b + 3)) & 1u),
-                                                lane);
-                code = (kin == b) ? cb : code;
-            }
+            for (int e = 0; e < 4 * RB; ++e) f[e] = (uint32_t)(__ballot((pos >> e) & 1u) >> sh);
+            code = pick_code(f, pick);
         }
         if (table < a.L && lane < 16 * RB && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
@@ -366,7 +403,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         load_a(kb, av);
         load_b(kb, bv);
     };
-    auto step = [&](const f4 (&av)[RB], const f4 (&bv)[TW]) {
+    // FIRST: the tile's first k block, whose products start the accumulators (a zero
+    // accumulator operand instead of clearing 16 RB TW registers).
+    auto step = [&](const f4 (&av)[RB], const f4 (&bv)[TW], auto first) {
+        constexpr bool FIRST = decltype(first)::value;
 #pragma unroll
         for (int b = 0; b < RB; ++b)
 #pragma unroll
@@ -377,45 +417,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             for (int t = 0; t < TW; ++t)
 #pragma unroll
                 for (int b = 0; b < RB; ++b)
-                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b][q], bv[t][q], acc[b][t], 0, 0, 0);
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        av[b][q], bv[t][q], (FIRST && q == 0) ? f4{0.f, 0.f, 0.f, 0.f} : acc[b][t], 0, 0, 0);
     };
+    const std::false_type more_k{};
 
     f4 ac[RB], bc[TW];
     if (kb1 > kb0) load_a(16 * kb0, ac);
     for (;;) {
         if (kb1 > kb0) load_b(16 * kb0, bc);
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            ss[b] = 0.f;
-#pragma unroll
-            for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int b = 0; b < RB; ++b) ss[b] = 0.f;
         // Block i + 1 is loaded while block i is multiplied; two blocks per trip so that the
         // operand registers alternate without copies.  Past the last full block the loads
         // read the partial block or the next rows and columns: in range, and unused unless
         // REM == 12, whose partial block it is.
-        int i = kb0;
-        for (; i + 2 <= kb1; i += 2) {
+        auto pair = [&](int i, auto first) {
             f4 an[RB], bn[TW];
             load(16 * (i + 1), an, bn);
-            step(ac, bc);
+            step(ac, bc, first);
             // Keep each block's norm updates (which wait for its loads) out of the previous
             // block's MFMA stream.
             __builtin_amdgcn_sched_barrier(0);
             load(16 * (i + 2), ac, bc);
-            step(an, bn);
+            step(an, bn, more_k);
             __builtin_amdgcn_sched_barrier(0);
-        }
-        if (i < kb1) {
+        };
+        auto single = [&](int i, auto first) {
             f4 an[RB], bn[TW];
             load(16 * (i + 1), an, bn);
-            step(ac, bc);
+            step(ac, bc, first);
             if constexpr (REM == 12) {
 #pragma unroll
                 for (int b = 0; b < RB; ++b) ac[b] = an[b];
 #pragma unroll
                 for (int t = 0; t < TW; ++t) bc[t] = bn[t];
             }
+        };
+        if (kb1 - kb0 >= 2) {
+            pair(kb0, std::true_type{});
+            int i = kb0 + 2;
+            for (; i + 2 <= kb1; i += 2) pair(i, more_k);
+            if (i < kb1) single(i, more_k);
+        } else if (kb1 > kb0) {
+            single(kb0, std::true_type{});
+        } else {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
         }
 
         // The partial block belongs to the last k quarter; the other quarters multiply
@@ -428,7 +478,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
 #pragma unroll
                 for (int b = 0; b < RB; ++b) ac[b] = f4{0.f, 0.f, 0.f, 0.f};
             }
-            step(ac, bc);
+            step(ac, bc, more_k);
         } else if constexpr (REM == 8) {
             typedef float f2 __attribute__((ext_vector_type(2)));
             const uint32_t kof = (uint32_t)(kb + 2 * kin) * 4u;
@@ -525,24 +575,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
 #pragma unroll
             for (int b = 0; b < RB; ++b) ss[b] = (s0[b] + s1[b]) + (s2[b] + s3[b]);
         }
-        // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
-        // row 16b + cl, lane l needs rows 16b + 4 kin + r.
-        float rbnd[4 * RB];
-#pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            // The four k groups' sums are added in FP32 (two more roundings: d/4 + 5 in all,
-            // well inside norm_up), then the root and products are taken in FP32: their few
-            // roundings are covered by the 2^-20 margin.
-            float s2 = ss[b];
-            s2 += __shfl_xor(s2, 16, 64);
-            s2 += __shfl_xor(s2, 32, 64);
-            const float rb = gx * sqrtf(fmaf(s2, a.norm_up, (float)(d + 16) * 0x1p-125f)) * (1.f + 0x1p-20f);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = __shfl(rb, 4 * kin + r, 64);
-        }
         float wcol[TW];
 #pragma unroll
         for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
+        // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
+        // row 16b + cl, lane l needs rows 16b + 4 kin + r.  The four k groups' sums are added
+        // in FP32 (two more roundings: d/4 + 5 in all, well inside norm_up), then the root and
+        // products are taken in FP32: their few roundings are covered by the 2^-20 margin.
+        // All row blocks go through each step together (the shuffles' latencies overlap).
+        float s2[RB], rbnd[4 * RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) s2[b] = ss[b] + __shfl_xor(ss[b], 16, 64);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) s2[b] += __shfl_xor(s2[b], 32, 64);
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            s2[b] = gx * __builtin_amdgcn_sqrtf(fmaf(s2[b], a.norm_up, (float)(d + 16) * 0x1p-125f)) * (1.f + 0x1p-20f);
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rbnd[4 * b + r] = __shfl(s2[b], 4 * kin + r, 64);
         sign_epilogue<TW, RB>(a, acc, rbnd, wcol, rbase, cbase, nv, lane, tmask);
         if (!more) break;
         v = v2;

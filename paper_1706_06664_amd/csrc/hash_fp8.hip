@@ -35,10 +35,19 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef int i4v __attribute__((ext_vector_type(4)));
 
-__device__ inline uint32_t select_code(u64 m0, u64 m1, u64 m2, u64 m3, int lane) {
-    const int r = lane & 3, g = (lane & 15) >> 2;
-    u64 m = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
-    return (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+// Sign packing.  Lane l stores row rho = l & 15 of 16-row tile l >> 4.  Tile b's ballot of
+// accumulator element r holds row 4g + r in bits 16g .. 16g + 15 (lane 16g + c holds column
+// c), so lane l needs ballot pick = 4 (l >> 4) + (l & 3) shifted right by 16 ((l & 15) >> 2).
+// f[e] is ballot e already shifted by the lane's amount; a select tree over the bits of pick
+// keeps the lane's own (masks, not branches or a switch).
+__device__ inline uint32_t pick_code(uint32_t (&f)[16], int pick) {
+#pragma unroll
+    for (int w = 1; w < 16; w <<= 1) {
+        const uint32_t m = 0u - (uint32_t)((pick & w) != 0);
+#pragma unroll
+        for (int i = 0; i + w < 16; i += 2 * w) f[i] = (f[i + w] & m) | (f[i] & ~m);
+    }
+    return f[0];
 }
 
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
@@ -249,6 +258,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     const int kin = lane >> 4, cl = lane & 15;
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = row0 + wm * 64 + lane;
+    const int pick = 4 * kin + (lane & 3), sh = 16 * ((lane & 15) >> 2);
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
     uint32_t rok = 0;
     float rA[16], rB[16];
@@ -260,20 +270,40 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
         rA[e] = a.rowA[g];
         rB[e] = a.rowB[g];
     }
+    float rAm = rA[0], rBm = rB[0];
+#pragma unroll
+    for (int e = 1; e < 16; ++e) {
+        rAm = __builtin_elementwise_maximum(rAm, rA[e]);
+        rBm = __builtin_elementwise_maximum(rBm, rB[e]);
+    }
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         const int table = (col0 >> 4) + wn * TW + t;
         const int cp = col0 + (wn * TW + t) * 16 + cl;
         const float cA = a.wbA[cp], cB = a.wbB[cp], cE = a.wbE[cp];
-        uint32_t umask = 0;
-        if (a.refine && cA >= 0.f) {
+        // Bit e of umask: element e lies inside its bound (NaN is uncertain too).  First one
+        // comparison of the smallest |p| against the bound of the lane's largest row factors
+        // (every factor is >= 0, so that bound is the largest; minimum and maximum keep a
+        // NaN), then, only where that fails somewhere in the wave, element by element.
+        const bool chk = a.refine && cA >= 0.f;
+        float amin = fabsf(acc[0][t][0]);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                float thr = fmaf(rA[e], cA, cE);
-                thr = fmaf(rB[e], cB, thr);
-                umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;
+        for (int e = 1; e < 16; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(acc[e >> 2][t][e & 3]));
+        const bool maybe = chk && !(amin > fmaf(rBm, cB, fmaf(rAm, cA, cE)));
+        uint32_t umask = 0;
+        if (__any(maybe)) {
+            // (The empty asm keeps the 16 bounds from being computed ahead of the test.)
+            float cAv = cA;
+            asm volatile("" : "+v"(cAv));
+            if (chk) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float thr = fmaf(rA[e], cAv, cE);
+                    thr = fmaf(rB[e], cB, thr);
+                    umask |= !(fabsf(acc[e >> 2][t][e & 3]) > thr) ? (1u << e) : 0u;
+                }
+                umask &= rok;
             }
-            umask &= rok;
         }
         if (a.refine == 2) {
             n_unc += __popc(umask);  // count only: the raw signs stand
@@ -311,13 +341,15 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
                 ++slot;
             }
         }
-        uint32_t code = 0;
+        uint32_t f[16];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t cb = select_code(__ballot(acc[b][t][0] > 0.f), __ballot(acc[b][t][1] > 0.f),
-                                            __ballot(acc[b][t][2] > 0.f), __ballot(acc[b][t][3] > 0.f), lane);
-            code = (kin == b) ? cb : code;
+        for (int e = 0; e < 16; ++e) {
+            f[e] = (uint32_t)(__ballot(acc[e >> 2][t][e & 3] > 0.f) >> sh);
+            // Shift each ballot as it is taken: selecting the unshifted scalar pairs first
+            // would cost two vector selects (and copies) per pair.
+            asm("" : "+v"(f[e]));
         }
+        const uint32_t code = pick_code(f, pick);
         if (table < a.L && orow < nv) a.codes[(int64_t)table * a.ldc + orow] = (uint16_t)(code & kmask);
     }
     if (__any(n_ref != 0 || n_unc != 0)) {
