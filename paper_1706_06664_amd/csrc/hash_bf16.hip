@@ -296,6 +296,7 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
         rBm = __builtin_elementwise_maximum(rBm, rB[e >> 2][e & 3]);
         rCm = __builtin_elementwise_maximum(rCm, rC[e >> 2][e & 3]);
     }
+    bool fast = true;  // wave-uniform
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         const int table = (col0 >> 4) + wn * TW + t;
@@ -307,14 +308,20 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
         // Bit e of umask: element e lies inside its bound (NaN is uncertain too).  First one
         // comparison of the smallest |p| against the bound of the lane's largest row factors
         // (every factor is >= 0, so that bound is the largest; minimum and maximum keep a
-        // NaN), then, only where that fails somewhere in the wave, element by element.
+        // NaN), then, only where that fails somewhere in the wave, element by element.  Once
+        // the pre-check has failed, the later tables skip it (data whose bounds are often hit
+        // would pay for both).
         const bool chk = a.refine && cA >= 0.f;
-        float amin = fabsf(p[0][0]);
+        bool exact = !fast;
+        if (fast) {
+            float amin = fabsf(p[0][0]);
 #pragma unroll
-        for (int e = 1; e < 16; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(p[e >> 2][e & 3]));
-        const bool maybe = chk && !(amin > fmaf(rCm, cC, fmaf(rBm, cB, fmaf(rAm, cA, cE))));
+            for (int e = 1; e < 16; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(p[e >> 2][e & 3]));
+            exact = __any(chk && !(amin > fmaf(rCm, cC, fmaf(rBm, cB, fmaf(rAm, cA, cE)))));
+            fast = !exact;
+        }
         uint32_t umask = 0;
-        if (__any(maybe)) {
+        if (exact) {
             // (The empty asm keeps the 16 bounds from being computed ahead of the test.)
             float cAv = cA;
             asm volatile("" : "+v"(cAv));

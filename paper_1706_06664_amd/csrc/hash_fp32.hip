@@ -95,6 +95,7 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
 #pragma unroll
     for (int e = 1; e < 4 * RB; ++e) rbmax = __builtin_elementwise_maximum(rbmax, rbnd[e]);
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;                // projections decided in place (queue full)
+    bool fast = true;  // wave-uniform
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
         if (!((tmask >> t) & 1u)) continue;  // a table another wave finishes
@@ -105,13 +106,18 @@ __device__ inline void sign_epilogue(const HashArgs& a, f4 (&acc)[RB][TW], const
         // Is any accumulator element of this lane inside its bound?  (NaN is uncertain too.)
         // First against the lane's largest bound (one comparison of the smallest |acc|; the
         // minimum keeps a NaN), then, only where that fails somewhere in the wave, element by
-        // element.
-        float amin = fabsf(acc[0][t][0]);
+        // element.  Once the pre-check has failed, the tile's later tables skip it (data whose
+        // bounds are often hit would pay for both).
+        bool exact = !fast;
+        if (fast) {
+            float amin = fabsf(acc[0][t][0]);
 #pragma unroll
-        for (int e = 1; e < 4 * RB; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(acc[e >> 2][t][e & 3]));
-        const bool maybe = chk && !(amin > fmaf(rbmax, wbv, a.eps_abs));
+            for (int e = 1; e < 4 * RB; ++e) amin = __builtin_elementwise_minimum(amin, fabsf(acc[e >> 2][t][e & 3]));
+            exact = __any(chk && !(amin > fmaf(rbmax, wbv, a.eps_abs)));
+            fast = !exact;
+        }
         bool unc = false;
-        if (__any(maybe)) {
+        if (exact) {
             // (The empty asm keeps these 4 RB bounds from being computed ahead of the test.)
             float wv = wbv;
             asm volatile("" : "+v"(wv));
@@ -351,6 +357,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
     const int d = a.d;
     const uint32_t xo = (uint32_t)(cl * d) * 4u, wo = (uint32_t)(cl * a.DP) * 4u;
     const int xstep = 16 * d * 4, wstep = 16 * a.DP * 4;  // bytes per 16-row / 16-column tile
+    // Scalar offsets of the row blocks and column tiles.  readfirstlane keeps each one a
+    // scalar operand: a uniform value that reaches a load through a phi the compiler places
+    // in a vector register would otherwise get a loop around the load.
+    auto xoff = [&](int b) { return __builtin_amdgcn_readfirstlane(b * xstep); };
+    auto woff = [&](int t) { return __builtin_amdgcn_readfirstlane(t * wstep); };
     const int nfull = d >> 4;  // full 16-wide k blocks; REM = d - 16 nfull (0, 4, 8 or 12)
     const int kb0 = nfull * kw / KS, kb1 = nfull * (kw + 1) / KS;  // this wave's full blocks
     const float gx = KS == 1 ? a.gx : a.gx_split;
@@ -391,13 +402,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         const uint32_t kof = (uint32_t)(kb + 4 * kin) * 4u;
 #pragma unroll
         for (int b = 0; b < RB; ++b)
-            av[b] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xs, xo + kof, b * xstep, 0));
+            av[b] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xs, xo + kof, xoff(b), 0));
     };
     auto load_b = [&](int kb, f4 (&bv)[TW]) {
         const uint32_t kof = (uint32_t)(kb + 4 * kin) * 4u;
 #pragma unroll
         for (int t = 0; t < TW; ++t)
-            bv[t] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(ws, wo + kof, t * wstep, 0));
+            bv[t] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(ws, wo + kof, woff(t), 0));
     };
     auto load = [&](int kb, f4 (&av)[RB], f4 (&bv)[TW]) {
         load_a(kb, av);
@@ -485,12 +496,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             f2 av[RB], bv[TW];
 #pragma unroll
             for (int b = 0; b < RB; ++b) {
-                av[b] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xs, xo + kof, b * xstep, 0));
+                av[b] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xs, xo + kof, xoff(b), 0));
                 if (tail_zero) av[b] = f2{0.f, 0.f};
             }
 #pragma unroll
             for (int t = 0; t < TW; ++t)
-                bv[t] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ws, wo + kof, t * wstep, 0));
+                bv[t] = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ws, wo + kof, woff(t), 0));
 #pragma unroll
             for (int b = 0; b < RB; ++b) ss[b] = fmaf(av[b][1], av[b][1], fmaf(av[b][0], av[b][0], ss[b]));
 #pragma unroll
@@ -505,12 +516,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
             float av[RB], bv[TW];
 #pragma unroll
             for (int b = 0; b < RB; ++b) {
-                av[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, xo + kof, b * xstep, 0));
+                av[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, xo + kof, xoff(b), 0));
                 if (tail_zero) av[b] = 0.f;
             }
 #pragma unroll
             for (int t = 0; t < TW; ++t)
-                bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ws, wo + kof, t * wstep, 0));
+                bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ws, wo + kof, woff(t), 0));
 #pragma unroll
             for (int b = 0; b < RB; ++b) ss[b] = fmaf(av[b], av[b], ss[b]);
 #pragma unroll
@@ -580,8 +591,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
         for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
         // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
         // row 16b + cl, lane l needs rows 16b + 4 kin + r.  The four k groups' sums are added
-        // in FP32 (two more roundings: d/4 + 5 in all, well inside norm_up), then the root and
-        // products are taken in FP32: their few roundings are covered by the 2^-20 margin.
+        // in FP32 (two more roundings: d/4 + 5 in all, well inside norm_up), then the scaled
+        // sum (one rounding), the hardware square root (within one ulp) and two products: at
+        // most 5 2^-24 relative below the exact value, covered by the 2^-20 margin.  The
+        // (d + 16) 2^-125 term keeps the root's argument a normal number.
         // All row blocks go through each step together (the shuffles' latencies overlap).
         float s2[RB], rbnd[4 * RB];
 #pragma unroll
