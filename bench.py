@@ -16,7 +16,7 @@ Headline workload (the `value`): connection-log shaped points, 494,021 x 120
 K = 15 bits, L = 50 tables, FP32 projections refined in FP64 inside the FP32
 error bound.  The other workloads (split-BF16 and e4m3 against FP32 on a dense
 4,000,000 x 1024 low-rank workload and a 1,000,000 x 4096 heavy-tailed one, the
-serving loop, the estimator study) go into a compact the benchmark spec block of the
+serving loop, the estimator study) go into a compact `workloads` block of the
 JSON line; their full records go to stderr and, with --detail PATH, to a file.
 
 Prints one JSON line on stdout.
@@ -594,7 +594,7 @@ def exact_score_runs(X, W, K, n_queries=4096, reps=5):
     return out
 
 
-def north_star_block(extra):
+def workloads_block(extra):
     """The compact summary the JSON line carries: BF16-vs-FP32 speed-ups with refined
     fractions, raw flip rates and the unrefined flips the oracle sample found, the e4m3 flip
     rate and score error, and the serving loop's rates and latencies."""
@@ -784,7 +784,7 @@ def main():
         "flagged": head["flagged"],
     }
     if extra:
-        out["north_star"] = north_star_block(extra)
+        out["workloads"] = workloads_block(extra)
     line = json.dumps(out, separators=(",", ":"))
     if args.detail:
         with open(args.detail, "w") as f:
