@@ -38,6 +38,8 @@
 // kernel: per k, a 128 x 128 tile loads 1 KB of split operands for 3 x 128 x 128
 // products (96 FLOP per byte), and two accumulator chains leave no registers for a
 // larger tile.
+#include <type_traits>
+
 #include "ace_internal.h"
 
 namespace ace {
@@ -183,14 +185,8 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     const int64_t row0 = tile_m * BM;
     const int col0 = (int)tile_n * NB;
 
+    // Started by the first k-step's MFMAs (a zero accumulator operand), not cleared.
     f4 accm[4][TW], accc[4][TW];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            accm[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-            accc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-        }
 
     // Stage fill: wave load i (i = 4 j + wave) moves one 1 KB tile (16 rows or columns by
     // 32 k) straight from global memory into LDS, lane l's 16 bytes at byte 16 l.  Row
@@ -223,7 +219,9 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
     // logical chunk l >> 4 of that tile row.
     const int fr = lane & 15;
     const int foff = fr * 64 + 16 * ((lane >> 4) ^ tile_chunk_swz(fr));
-    auto step = [&](const char* stage) {
+    auto step = [&](const char* stage, auto first) {
+        constexpr bool FIRST = decltype(first)::value;
+        const f4 z = f4{0.f, 0.f, 0.f, 0.f};
         bf8 ah[4], al[4], bh[TW], bl[TW];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -241,54 +239,81 @@ __global__ __launch_bounds__(256, 2) void hash_bf16_kernel(const HashArgs a) {
         for (int t = 0; t < TW; ++t) {
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                accm[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bh[t], accm[b][t], 0, 0, 0);
+                accm[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bh[t], FIRST ? z : accm[b][t], 0, 0, 0);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bl[t], accc[b][t], 0, 0, 0);
+                accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b], bl[t], FIRST ? z : accc[b][t], 0, 0, 0);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 accc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[b], bh[t], accc[b][t], 0, 0, 0);
         }
     };
+    const std::false_type later{};
 
     // Two LDS stages: while one is read by the MFMAs, the next k-step streams into the
     // other.  One barrier per k-step: after it, stage s is complete and every wave has
     // finished reading stage s ^ 1 (its fragments were consumed by the previous step).
     const int nk = a.DP / BK;
     fill(st0, 0);
-    for (int it = 0; it < nk; it += 2) {
+    wait_lds_loads();
+    __syncthreads();
+    if (1 < nk) fill(st1, BK);
+    step(st0, std::true_type{});
+    for (int it = 1; it < nk; it += 2) {  // k-step it from stage 1, it + 1 from stage 0
         wait_lds_loads();
         __syncthreads();
-        if (it + 1 < nk) fill(st1, (it + 1) * BK);
-        step(st0);
+        if (it + 1 < nk) fill(st0, (it + 1) * BK);
+        step(st1, later);
         if (it + 1 >= nk) break;
         wait_lds_loads();
         __syncthreads();
-        if (it + 2 < nk) fill(st0, (it + 2) * BK);
-        step(st1);
+        if (it + 2 < nk) fill(st1, (it + 2) * BK);
+        step(st0, later);
     }
     const int kin = lane >> 4, cl = lane & 15;
     const uint32_t kmask = (a.K >= 16) ? 0xFFFFu : ((1u << a.K) - 1u);
     const int64_t orow = row0 + wm * 64 + lane;
     const int pick = 4 * kin + (lane & 3), sh = 16 * ((lane & 15) >> 2);
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
-    uint32_t rok = 0;
+    const int64_t rw = row0 + wm * 64;  // this wave's first row
+    uint32_t rok = 0xFFFFu;             // rows past the batch (last row tile only) take no bits
+    if (rw + 64 > nv) {
+        rok = 0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-        rok |= (row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
-    // Row norms of this lane's 16 rows (four consecutive rows per row block); rows past
-    // n read row n-1's values, which only matter for rows that store nothing.
+        for (int e = 0; e < 16; ++e) rok |= (rw + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+    }
+    // Row norms of this lane's 16 rows (four consecutive rows per row block): one 16-byte
+    // load per block and norm where the wave's rows all exist and the arrays are 16-byte
+    // aligned; otherwise one value at a time, rows past n reading row n-1's values (which
+    // only matter for rows that store nothing).
     float rA[4][4], rB[4][4], rC[4][4];
+    const bool vec_norms = rw + 64 <= a.n && ((reinterpret_cast<uintptr_t>(a.rowA) | reinterpret_cast<uintptr_t>(a.rowB) |
+                                               reinterpret_cast<uintptr_t>(a.rowC)) & 15u) == 0;
+    if (vec_norms) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b) {
+            const int64_t g = rw + 16 * b + 4 * kin;
+            const f4 va = *reinterpret_cast<const f4*>(a.rowA + g), vb = *reinterpret_cast<const f4*>(a.rowB + g),
+                     vc = *reinterpret_cast<const f4*>(a.rowC + g);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int64_t g = row0 + wm * 64 + 16 * b + 4 * kin + r;
-            g = g < a.n ? g : a.n - 1;
-            rA[b][r] = a.rowA[g];
-            rB[b][r] = a.rowB[g];
-            rC[b][r] = a.rowC[g];
+            for (int r = 0; r < 4; ++r) {
+                rA[b][r] = va[r];
+                rB[b][r] = vb[r];
+                rC[b][r] = vc[r];
+            }
         }
+    } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t g = rw + 16 * b + 4 * kin + r;
+                g = g < a.n ? g : a.n - 1;
+                rA[b][r] = a.rowA[g];
+                rB[b][r] = a.rowB[g];
+                rC[b][r] = a.rowC[g];
+            }
+    }
     float rAm = rA[0][0], rBm = rB[0][0], rCm = rC[0][0];
 #pragma unroll
     for (int e = 1; e < 16; ++e) {
