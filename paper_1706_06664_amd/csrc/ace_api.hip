@@ -126,7 +126,7 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->rcnt, c->err, c->thr,
+    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->mpart, c->rcnt, c->err, c->thr,
                     c->sgn, c->sgn_lane};
     ws_free(&c->ws);
     for (void* p : ptrs)
@@ -498,6 +498,9 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->mom, sizeof(u64) * 4);
+    // Per-block moments of a score launch over one workspace chunk (either score kernel).
+    c->mpart_cap = (c->ws_rows + 255) / 256 + 1;
+    st = st ? st : dev_alloc(c, (void**)&c->mpart, sizeof(u64) * 3 * (size_t)c->mpart_cap);
     st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
@@ -746,7 +749,8 @@ ace_status ace_score(ace_ctx c, const float* X, int64_t n, float* s_out, uint32_
         {
             Bracket br(c, s, CLS_SCORE, m);
             st = check(c, launch_score(c->ws.codes, m, m, c->cfg.K, c->cfg.L, c->counts, c->cbits,
-                                       s_out ? s_out + r0 : nullptr, T_out ? T_out + r0 : nullptr, c->mom, s));
+                                       s_out ? s_out + r0 : nullptr, T_out ? T_out + r0 : nullptr, c->mom, s,
+                                       c->mpart, c->mpart_cap));
         }
         if (st) return st;
     }
@@ -763,7 +767,7 @@ ace_status ace_score_codes(ace_ctx c, const uint16_t* codes, int64_t n, float* s
     if (take_injected_failure(c)) return ACE_E_DEVICE;
     DeviceGuard g(c->cfg.device);
     return check(c, launch_score(codes, n, n, c->cfg.K, c->cfg.L, c->counts, c->cbits, s_out, T_out, c->mom,
-                                 (hipStream_t)stream));
+                                 (hipStream_t)stream, c->mpart, c->mpart_cap));
 }
 
 ace_status ace_hash(ace_ctx c, const float* X, int64_t n, uint16_t* codes, uint16_t* refined, void* stream) {

@@ -49,6 +49,8 @@ struct ace_ctx_s {
     ace::u64* S2 = nullptr;           // [L]
     ace::u64* S3 = nullptr;           // [L][2]
     ace::u64* mom = nullptr;          // m, sum T, sum T^2 lo, hi
+    ace::u64* mpart = nullptr;        // [mpart_cap][3] per-block moments of one score launch
+    int64_t mpart_cap = 0;
     ace::u64* rcnt = nullptr;         // bits refined, bits flipped, bits inside the bound left unrefined,
                                       // increments dropped by saturated 16-bit counters
     unsigned* err = nullptr;     // device error flags (1 = a count went below zero)

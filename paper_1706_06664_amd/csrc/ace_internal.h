@@ -142,8 +142,11 @@ hipError_t init_struct_attributes();
 hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, int sign,
                                void* counts, int counter_bits, u64* S2, u64* S3, unsigned* err, u64* drops,
                                hipStream_t s);
+// mpart (may be null): room for mpart_cap per-block moment entries (3 u64 each); a launch
+// of more than 64 blocks that fits writes them there and adds them to mom in one more block.
 hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
-                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s);
+                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s,
+                        u64* mpart = nullptr, int64_t mpart_cap = 0);
 hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode,
                             double alpha, DevThresh* out, hipStream_t s);
 hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);

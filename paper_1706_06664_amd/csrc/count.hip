@@ -310,13 +310,29 @@ __global__ __launch_bounds__(256) void update_direct_kernel(const uint16_t* __re
     }
 }
 
+// A block's (sum T, sum T^2) go to the scored-set moments: straight into mom with atomics,
+// or, with mpart, as block b's entry mpart[3 b .. 3 b + 2] for mom_reduce_kernel.  Atomics
+// on one address from every block of a large grid are served one after another.
+__device__ inline void put_moments(u64 sT, u64 lo, u64 hi, int64_t m, u64* __restrict__ mom,
+                                   u64* __restrict__ mpart) {
+    if (mpart) {
+        mpart[3 * (int64_t)blockIdx.x] = sT;
+        mpart[3 * (int64_t)blockIdx.x + 1] = lo;
+        mpart[3 * (int64_t)blockIdx.x + 2] = hi;
+    } else {
+        if (m) atomicAdd(&mom[0], (u64)m);
+        atomicAdd(&mom[1], sT);
+        atomic_add_u128(&mom[2], lo, hi);
+    }
+}
+
 // Query phase: T(q) = sum_j A_j[H_j(q)], s = T / L; one thread per row.  The block's
-// (m, sum T, sum T^2) are added to the scored-set moments mom[0..3].
+// (m, sum T, sum T^2) are added to the scored-set moments mom[0..3] (put_moments).
 template <typename CT>
 __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__ codes, int64_t ldc, int64_t n,
                                                     int K, int L, const CT* __restrict__ counts,
                                                     float* __restrict__ s_out, uint32_t* __restrict__ T_out,
-                                                    u64* __restrict__ mom) {
+                                                    u64* __restrict__ mom, u64* __restrict__ mpart) {
     __shared__ u64 red[3 * 4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t T = 0;
@@ -345,10 +361,7 @@ __global__ __launch_bounds__(256) void score_kernel(const uint16_t* __restrict__
     block_sum3(sT, lo, hi, red);
     if (threadIdx.x == 0) {
         const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
-        const int64_t m = min((int64_t)blockDim.x, n - r0);
-        atomicAdd(&mom[0], (u64)m);
-        atomicAdd(&mom[1], sT);
-        atomic_add_u128(&mom[2], lo, hi);
+        put_moments(sT, lo, hi, min((int64_t)blockDim.x, n - r0), mom, mpart);
     }
 }
 
@@ -361,7 +374,7 @@ template <typename CT>
 __global__ __launch_bounds__(256) void score_tables_kernel(const uint16_t* __restrict__ codes, int64_t ldc, int64_t n,
                                                            int K, int L, const CT* __restrict__ counts,
                                                            float* __restrict__ s_out, uint32_t* __restrict__ T_out,
-                                                           u64* __restrict__ mom) {
+                                                           u64* __restrict__ mom, u64* __restrict__ mpart) {
     __shared__ u64 red[3 * 4];
     const int64_t G = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, i1 = i0 + G;
@@ -391,8 +404,22 @@ __global__ __launch_bounds__(256) void score_tables_kernel(const uint16_t* __res
         add128(lo, hi, (u64)t2, (u64)(t2 >> 64));
     }
     block_sum3(sT, lo, hi, red);
+    if (threadIdx.x == 0) put_moments(sT, lo, hi, blockIdx.x == 0 ? n : 0, mom, mpart);
+}
+
+// The per-block entries of a score launch (nb of them) summed in one block and added to the
+// scored-set moments with the launch's row count m.
+__global__ __launch_bounds__(1024) void mom_reduce_kernel(const u64* __restrict__ mpart, int64_t nb, int64_t m,
+                                                          u64* __restrict__ mom) {
+    __shared__ u64 red[3 * 16];
+    u64 sT = 0, lo = 0, hi = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        sT += mpart[3 * b];
+        add128(lo, hi, mpart[3 * b + 1], mpart[3 * b + 2]);
+    }
+    block_sum3(sT, lo, hi, red);
     if (threadIdx.x == 0) {
-        if (blockIdx.x == 0) atomicAdd(&mom[0], (u64)n);
+        atomicAdd(&mom[0], (u64)m);
         atomicAdd(&mom[1], sT);
         atomic_add_u128(&mom[2], lo, hi);
     }
@@ -591,25 +618,32 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
 }
 
 hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
-                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s) {
+                        int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s, u64* mpart,
+                        int64_t mpart_cap) {
     if (n <= 0) return hipSuccess;
-    if (n >= 131072) {   // at least 256 workgroups of the table-by-table kernel
-        const unsigned blocks = (unsigned)(((n + 1) / 2 + 255) / 256);
+    const bool tables = n >= 131072;   // at least 256 workgroups of the table-by-table kernel
+    const int64_t nb = tables ? ((n + 1) / 2 + 255) / 256 : (n + 255) / 256;
+    // Past 64 blocks the moments go through per-block entries and one reducing block.
+    u64* mp = (mpart && nb > 64 && nb <= mpart_cap) ? mpart : nullptr;
+    if (tables) {
         if (counter_bits == 16)
-            hipLaunchKernelGGL(score_tables_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, codes, ldc, n, K, L,
-                               reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom);
+            hipLaunchKernelGGL(score_tables_kernel<uint16_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K,
+                               L, reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom, mp);
         else
-            hipLaunchKernelGGL(score_tables_kernel<int32_t>, dim3(blocks), dim3(256), 0, s, codes, ldc, n, K, L,
-                               reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom);
-        return hipGetLastError();
+            hipLaunchKernelGGL(score_tables_kernel<int32_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
+                               reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom, mp);
+    } else {
+        if (counter_bits == 16)
+            hipLaunchKernelGGL(score_kernel<uint16_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
+                               reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom, mp);
+        else
+            hipLaunchKernelGGL(score_kernel<int32_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
+                               reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom, mp);
     }
-    const int64_t nb = (n + 255) / 256;
-    if (counter_bits == 16)
-        hipLaunchKernelGGL(score_kernel<uint16_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
-                           reinterpret_cast<const uint16_t*>(counts), s_out, T_out, mom);
-    else
-        hipLaunchKernelGGL(score_kernel<int32_t>, dim3((unsigned)nb), dim3(256), 0, s, codes, ldc, n, K, L,
-                           reinterpret_cast<const int32_t*>(counts), s_out, T_out, mom);
+    if (!mp) return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mom_reduce_kernel, dim3(1), dim3(1024), 0, s, mp, nb, n, mom);
     return hipGetLastError();
 }
 

@@ -93,6 +93,9 @@ def full_parity(X: np.ndarray, W: np.ndarray, K: int, L: int, device="cuda", sig
     s_gn = s_g.cpu().numpy()
 
     assert np.array_equal(counts_g.astype(np.int64), recount(codes_g, K)), "counts != recount of GPU codes"
+    # T is the sum of the GPU's counts at the GPU's codes, whichever kernel gathered them
+    T_own = counts_g.astype(np.int64)[np.arange(L)[None, :], codes_g.astype(np.int64) & ((1 << K) - 1)].sum(axis=1)
+    assert np.array_equal(T_gn, T_own), "T != gather of the GPU's counts at its codes"
     S2_g, S3_g = ace.table_stats()
     if n_diff == 0:
         assert np.array_equal(counts_g.astype(np.int64), sk.counts)

@@ -264,6 +264,22 @@ def test_refine_queue_full_path(precision):
     assert np.array_equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1] and res[0][1] >= 64 * K * L
     assert np.array_equal(res[0][2], res[1][2])
+    # The query phase with the same short queues (the FP32 kernel gathers the counts of the
+    # codes it decided in place, and leaves rows with queued bits for the full gather).
+    T_ref = None
+    for q in (0, 10):
+        ace = ACE(W, K, L, precision=precision)
+        assert ace.lib.ace_debug_set_refine_queue(ace.h, q) == 0
+        ace.insert(Xd)
+        _, T = ace.score(Xd)
+        T = T.cpu().numpy().view(np.uint32).astype(np.int64)
+        cg = res[0][0].astype(np.int64)
+        own = ace.counts().astype(np.int64)[np.arange(L)[None, :], cg].sum(axis=1)
+        assert np.array_equal(T, own)
+        if T_ref is not None:
+            assert np.array_equal(T, T_ref)
+        T_ref = T
+        ace.close()
 
 
 @pytest.mark.parametrize("bits", [32, 16])
@@ -294,3 +310,56 @@ def test_score_large_batches_from_codes(bits, n):
     assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
     check_thresh(ace.threshold("scored", 1.0), th_o)
     ace.close()
+
+
+@pytest.mark.parametrize("K,L,bits,chunk", [(15, 50, 32, 0), (16, 7, 32, 1000), (12, 13, 16, 0), (10, 3, 32, 333)])
+def test_score_matches_codes_path(K, L, bits, chunk):
+    """ace_score (hash, FP64 pass, gather per chunk) against ace_score_codes on the same codes
+    in a second context with the same counts: every T and s, and the scored-set statistics
+    (per-block moments reduced in one more block above 64 blocks, atomics below).  Zero rows
+    (every bit refined), near-orthogonal rows (some refined bits), random rows; ragged n,
+    16-bit counters, several chunks."""
+    import torch
+    from paper_1706_06664_amd import ACE, codes_as_uint16
+    from tests.parity import check_thresh
+    rng = np.random.default_rng(K * 1000 + L)
+    d = 36
+    W = projection_matrix(d, K, L, K + L)
+    zero = np.zeros((97, d), np.float32)
+    near = []
+    for _ in range(600):
+        y = rng.standard_normal(d)
+        c = rng.integers(0, K * L)
+        w = W[:, c].astype(np.float64)
+        near.append((y - (y @ w) / (w @ w) * w).astype(np.float32))
+    X = np.concatenate([rng.standard_normal((23450, d)).astype(np.float32), zero, np.array(near),
+                        rng.standard_normal((1789, d)).astype(np.float32)], axis=0)
+    Xd = torch.from_numpy(X).cuda()
+    kw = dict(counter_bits=bits, max_batch_rows=chunk)
+    a = ACE(W, K, L, **kw)
+    b = ACE(W, K, L, **kw)
+    a.insert(Xd)
+    b.insert(Xd)
+    s_a, T_a = a.score(Xd)
+    codes = b.hash(Xd)
+    s_b, T_b = b.score_codes(codes)
+    assert a.counters()["bits_refined"] >= 97 * K * L
+    assert torch.equal(T_a, T_b)
+    assert torch.equal(s_a, s_b)
+    cg = codes_as_uint16(codes).astype(np.int64)
+    own = a.counts().astype(np.int64)[np.arange(L)[None, :], cg].sum(axis=1)
+    Tn = T_a.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(Tn, own)
+    ta, tb = a.threshold("scored", 1.0), b.threshold("scored", 1.0)
+    check_thresh(ta, tb)
+    # the moments themselves, from T on the host
+    import math
+    n = len(Tn)
+    Ti = [int(v) for v in Tn]
+    S1, S2 = sum(Ti), sum(v * v for v in Ti)
+    mu = S1 / (n * L)
+    sd = math.sqrt(n * S2 - S1 * S1) / (n * L)
+    assert ta["m_scored"] == n
+    assert abs(ta["mu_scored"] - mu) <= 1e-12 * mu and abs(ta["sigma"] - sd) <= 1e-9 * sd
+    a.close()
+    b.close()
