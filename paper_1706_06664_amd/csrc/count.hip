@@ -162,25 +162,51 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
     for (; i < r1; i += bd) add(cj[i] & bmask);
     __syncthreads();
     u64 s2 = 0, s3lo = 0, s3hi = 0, dropped = 0;
-    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
-        const uint32_t h = PACK16 ? ((hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu) : hist[b];
-        if (h) {
-            const int32_t delta = sign > 0 ? (int32_t)h : -(int32_t)h;
-            int32_t old, moved;
-            if (C16) {
-                int32_t nv;
+    auto bucket = [&](int64_t b) -> uint32_t {
+        return PACK16 ? ((hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu) : hist[b];
+    };
+    if constexpr (C16) {
+        for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+            const uint32_t h = bucket(b);
+            if (h) {
+                const int32_t delta = sign > 0 ? (int32_t)h : -(int32_t)h;
+                int32_t old, nv;
                 update16(reinterpret_cast<uint32_t*>(counts_v) + (((int64_t)j * B) >> 1), b, delta, old, nv, err);
-                moved = nv - old;
-                if (sign > 0) dropped += (u64)(delta - moved);
-            } else {
-                old = atomicAdd(reinterpret_cast<int32_t*>(counts_v) + (int64_t)j * B + b, delta);
-                if ((int64_t)old + delta < 0) atomicOr(err, 1u);
-                moved = delta;
+                if (sign > 0) dropped += (u64)(delta - (nv - old));
+                u64 d2, d3lo, d3hi;
+                sq_cube_delta(old, nv - old, d2, d3lo, d3hi);
+                s2 += d2;
+                add128(s3lo, s3hi, d3lo, d3hi);
             }
-            u64 d2, d3lo, d3hi;
-            sq_cube_delta(old, moved, d2, d3lo, d3hi);
-            s2 += d2;
-            add128(s3lo, s3hi, d3lo, d3hi);
+        }
+    } else {
+        // Eight buckets per thread and pass, their returning atomics all issued before the
+        // first old value is used (one at a time, each pass would wait a full round trip
+        // per bucket).
+        constexpr int U = 8;
+        int32_t* cnt = reinterpret_cast<int32_t*>(counts_v) + (int64_t)j * B;
+        for (int64_t b0 = threadIdx.x; b0 < B; b0 += U * blockDim.x) {
+            int32_t delta[U], old[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t b = b0 + u * (int64_t)blockDim.x;
+                const uint32_t h = b < B ? bucket(b) : 0u;
+                delta[u] = sign > 0 ? (int32_t)h : -(int32_t)h;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                old[u] = 0;
+                if (delta[u] != 0) old[u] = atomicAdd(cnt + b0 + u * (int64_t)blockDim.x, delta[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (delta[u] == 0) continue;
+                if ((int64_t)old[u] + delta[u] < 0) atomicOr(err, 1u);
+                u64 d2, d3lo, d3hi;
+                sq_cube_delta(old[u], delta[u], d2, d3lo, d3hi);
+                s2 += d2;
+                add128(s3lo, s3hi, d3lo, d3hi);
+            }
         }
     }
     if (C16) {
