@@ -777,7 +777,7 @@ def main():
                    "n": n, "d": d, "K": K, "L": L, "precision": "fp32", "refine": True},
         "roofline": r4(roof),
         "cpu_baseline": r4(base) if base else None,
-        "hbm": r4({k: {"kernel": {"update": "update_lds_kernel", "score": "score_tables_kernel"}.get(k, k), "ms": v["ms"],
+        "hbm": r4({k: {"kernel": {"update": "update_lds_kernel", "score": "score_tables_kernel + mom_reduce_kernel"}.get(k, k), "ms": v["ms"],
                        "frac": v["frac"]} for k, v in head["hbm"].items()}),
         "phase_ms_per_step": r4(head["phase_ms_per_step"]),
         "refined_bit_frac": r4(head["refined_bit_frac"]),
