@@ -22,6 +22,8 @@
 // (fp8_tiled_index); each k-step moves whole tiles from global memory straight into one
 // of two LDS stages while the MFMAs read the other.  Lane l supplies the 16 k of chunk
 // l / 16 from both 64-byte halves of its row or column (the same k for both operands).
+#include <type_traits>
+
 #include "ace_internal.h"
 
 namespace ace {
@@ -186,11 +188,7 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     const int64_t row0 = tile_m * BM;
     const int col0 = (int)tile_n * NB;
 
-    f4 acc[4][TW];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int t = 0; t < TW; ++t) acc[b][t] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 acc[4][TW];  // started by the first k-step's products (a zero accumulator operand)
 
     // Stage fill: wave load i (i = 4 j + wave) moves one 1 KB sub-tile (16 rows or columns,
     // one 64-byte half of the k-step) straight into LDS, lane l's 16 bytes at byte 16 l.
@@ -224,7 +222,9 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
         const i4v lo = *reinterpret_cast<const i4v*>(p), hi = *reinterpret_cast<const i4v*>(p + 1024);
         return i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     };
-    auto step = [&](const uint8_t* stage) {
+    auto step = [&](const uint8_t* stage, auto first) {
+        constexpr bool FIRST = decltype(first)::value;
+        const f4 z = f4{0.f, 0.f, 0.f, 0.f};
         i8v af[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) af[b] = frag(stage + (wm * 4 + b) * 2048 + foff);
@@ -233,8 +233,8 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
             const i8v bf = frag(stage + A_BYTES + (wn * TW + t) * 2048 + foff);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                acc[b][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[b], bf, acc[b][t], 0, 0, 0, 127, 0,
-                                                                             127);
+                acc[b][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[b], bf, FIRST ? z : acc[b][t], 0, 0,
+                                                                             0, 127, 0, 127);
         }
     };
 
@@ -242,17 +242,22 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     // other.  One barrier per k-step: after it, stage s is complete and every wave has
     // finished reading stage s ^ 1 (its fragments were consumed by the previous step).
     const int nk = a.DP / BKB;
+    const std::false_type later{};
     fill(st0, 0);
-    for (int it = 0; it < nk; it += 2) {
+    wait_lds_loads();
+    __syncthreads();
+    if (1 < nk) fill(st1, BKB);
+    step(st0, std::true_type{});
+    for (int it = 1; it < nk; it += 2) {  // k-step it from stage 1, it + 1 from stage 0
         wait_lds_loads();
         __syncthreads();
-        if (it + 1 < nk) fill(st1, (it + 1) * BKB);
-        step(st0);
+        if (it + 1 < nk) fill(st0, (it + 1) * BKB);
+        step(st1, later);
         if (it + 1 >= nk) break;
         wait_lds_loads();
         __syncthreads();
-        if (it + 2 < nk) fill(st0, (it + 2) * BKB);
-        step(st1);
+        if (it + 2 < nk) fill(st1, (it + 2) * BKB);
+        step(st0, later);
     }
 
     const int kin = lane >> 4, cl = lane & 15;
@@ -260,15 +265,39 @@ __global__ __launch_bounds__(256, 2) void hash_fp8_kernel(const HashArgs a) {
     const int64_t orow = row0 + wm * 64 + lane;
     const int pick = 4 * kin + (lane & 3), sh = 16 * ((lane & 15) >> 2);
     uint32_t n_ref = 0, n_flip = 0, n_unc = 0;
-    uint32_t rok = 0;
-    float rA[16], rB[16];
+    const int64_t rw = row0 + wm * 64;  // this wave's first row
+    uint32_t rok = 0xFFFFu;             // rows past the batch (last row tile only) take no bits
+    if (rw + 64 > nv) {
+        rok = 0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        int64_t g = row0 + wm * 64 + 16 * (e >> 2) + 4 * kin + (e & 3);
-        rok |= (g < nv) ? (1u << e) : 0u;
-        g = g < a.n ? g : a.n - 1;
-        rA[e] = a.rowA[g];
-        rB[e] = a.rowB[g];
+        for (int e = 0; e < 16; ++e) rok |= (rw + 16 * (e >> 2) + 4 * kin + (e & 3) < nv) ? (1u << e) : 0u;
+    }
+    // Row factors of this lane's 16 rows (four consecutive rows per row block): one 16-byte
+    // load per block and factor where the wave's rows all exist and the arrays are 16-byte
+    // aligned; otherwise one value at a time, rows past n reading row n-1's values (which
+    // only matter for rows that store nothing).
+    float rA[16], rB[16];
+    const bool vec_norms =
+        rw + 64 <= a.n && ((reinterpret_cast<uintptr_t>(a.rowA) | reinterpret_cast<uintptr_t>(a.rowB)) & 15u) == 0;
+    if (vec_norms) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t g = rw + 16 * b + 4 * kin;
+            const f4 va = *reinterpret_cast<const f4*>(a.rowA + g), vb = *reinterpret_cast<const f4*>(a.rowB + g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                rA[4 * b + r] = va[r];
+                rB[4 * b + r] = vb[r];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int64_t g = rw + 16 * (e >> 2) + 4 * kin + (e & 3);
+            g = g < a.n ? g : a.n - 1;
+            rA[e] = a.rowA[g];
+            rB[e] = a.rowB[g];
+        }
     }
     float rAm = rA[0], rBm = rB[0];
 #pragma unroll
