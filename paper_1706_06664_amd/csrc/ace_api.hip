@@ -126,11 +126,12 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->mpart, c->rcnt, c->err, c->thr,
+    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->mpart, c->rcnt, c->err,
                     c->sgn, c->sgn_lane};
     ws_free(&c->ws);
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->thr) (void)hipHostFree(c->thr);
 }
 
 ace_status enter(ace_ctx c) {
@@ -503,7 +504,13 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
     st = st ? st : dev_alloc(c, (void**)&c->mpart, sizeof(u64) * 3 * (size_t)c->mpart_cap);
     st = st ? st : dev_alloc(c, (void**)&c->rcnt, sizeof(u64) * 4);
     st = st ? st : dev_alloc(c, (void**)&c->err, sizeof(unsigned) * 4);
-    st = st ? st : dev_alloc(c, (void**)&c->thr, sizeof(DevThresh));
+    // The threshold result goes straight to coherent pinned host memory: no copy after the
+    // kernel, and the stream synchronisation that ends the call makes it visible.
+    if (!st && (hipHostMalloc((void**)&c->thr, sizeof(DevThresh), hipHostMallocCoherent) != hipSuccess ||
+                hipHostGetDevicePointer((void**)&c->thr_dev, c->thr, 0) != hipSuccess)) {
+        (void)hipGetLastError();
+        st = ACE_E_NOMEM;
+    }
     st = st ? st : ws_alloc(c, &c->ws, c->ws_rows);
     c->list_cap = c->ws.list_alloc;
     if (signs) {
@@ -807,16 +814,13 @@ ace_status ace_threshold(ace_ctx c, int32_t mode, double alpha, void* stream, ac
     hipStream_t s = (hipStream_t)stream;
     {
         Bracket br(c, s, CLS_OTHER);
-        st = check(c, launch_threshold(c->n_total, c->cfg.L, c->S2, c->S3, c->mom, mode, alpha, c->thr, s));
+        st = check(c, launch_threshold(c->n_total, c->cfg.L, c->S2, c->S3, c->mom, c->err, mode, alpha, c->thr_dev,
+                                       s));
     }
     if (st) return st;
-    DevThresh r;
-    unsigned errs[4];
-    hipError_t e = hipMemcpyAsync(&r, c->thr, sizeof(r), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(errs, c->err, sizeof(errs), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if ((st = check(c, e))) return st;
-    if (errs[0]) {
+    if ((st = check(c, hipStreamSynchronize(s)))) return st;
+    const DevThresh r = *c->thr;
+    if (r.err) {
         c->sticky = ACE_E_STATE;
         return ACE_E_STATE;
     }

@@ -54,7 +54,8 @@ struct ace_ctx_s {
     ace::u64* rcnt = nullptr;         // bits refined, bits flipped, bits inside the bound left unrefined,
                                       // increments dropped by saturated 16-bit counters
     unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
-    ace::DevThresh* thr = nullptr;
+    ace::DevThresh* thr = nullptr;      // pinned host memory the threshold kernel writes
+    ace::DevThresh* thr_dev = nullptr;  // its device address
     ace::Workspace ws;             // workspace of the stream-ordered calls
     int64_t ws_rows = 0;           // rows per internal chunk
     ace::u64 list_cap = 0;              // queue entries used per chunk (<= allocated)

@@ -121,6 +121,8 @@ struct DevThresh {
     int64_t n, m_scored;
     double mu, mu_scored, sigma, sigma_table, tau;
     int32_t mode, status;
+    uint32_t err;          // the context's error word 0 (a count went below zero) at the launch
+    uint32_t pad;
 };
 
 // Launchers (enqueue only; return the launch error).
@@ -147,8 +149,9 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
 hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
                         int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s,
                         u64* mpart = nullptr, int64_t mpart_cap = 0);
-hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode,
-                            double alpha, DevThresh* out, hipStream_t s);
+// out may be host memory mapped for the device (the result then needs no copy).
+hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, const unsigned* err,
+                            int mode, double alpha, DevThresh* out, hipStream_t s);
 hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);
 hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L, u64* S2, u64* S3, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

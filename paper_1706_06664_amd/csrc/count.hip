@@ -467,7 +467,8 @@ __device__ inline double u128_to_double(u64 lo, u64 hi) {
 // per-table deviations), block sums, then thread 0 finishes in FP64.
 __global__ __launch_bounds__(256) void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2,
                                                         const u64* __restrict__ S3, const u64* __restrict__ mom,
-                                                        int mode, double alpha, DevThresh* __restrict__ out) {
+                                                        const unsigned* __restrict__ err, int mode, double alpha,
+                                                        DevThresh* __restrict__ out) {
     __shared__ u64 red[3 * 4];
     __shared__ double dsum[4];
     u64 s2lo = 0, s2hi = 0, unused = 0;
@@ -492,6 +493,8 @@ __global__ __launch_bounds__(256) void threshold_kernel(int64_t n, int L, const 
     r.m_scored = (int64_t)mom[0];
     r.mode = mode;
     r.status = 0;
+    r.err = err[0];
+    r.pad = 0;
     // sum_j S2_j reaches 2^63 well inside the INT32_MAX insert cap (L tables of n^2 each):
     // it is summed and converted in 128 bits.
     r.mu = n > 0 ? u128_to_double(s2lo, s2hi) / ((double)n * (double)L) : 0.0;
@@ -673,9 +676,9 @@ hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, in
     return hipGetLastError();
 }
 
-hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, int mode, double alpha,
-                            DevThresh* out, hipStream_t s) {
-    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(256), 0, s, n, L, S2, S3, mom, mode, alpha, out);
+hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, const unsigned* err,
+                            int mode, double alpha, DevThresh* out, hipStream_t s) {
+    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(256), 0, s, n, L, S2, S3, mom, err, mode, alpha, out);
     return hipGetLastError();
 }
 
