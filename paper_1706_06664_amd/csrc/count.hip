@@ -139,8 +139,9 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
     const int64_t r1 = min(n, r0 + rows_per_block);
     const uint16_t* cj = codes + (int64_t)j * ldc;
     const uint32_t bmask = (uint32_t)(B - 1);  // codes from callers are reduced to K bits
-    // Four rows per thread per pass: their codes are loaded before the first merge test,
-    // which needs its row's code in a scalar register.
+    // Sixteen rows per thread per pass (then four, then one): their codes are all loaded
+    // before the first merge test, which needs its row's code in a scalar register, so a
+    // pass waits for one round trip to memory instead of one per row.
     auto add = [&](uint32_t b) {
         const uint32_t m = merge_equal_buckets(b);
         if (!m) return;
@@ -151,6 +152,13 @@ __global__ __launch_bounds__(HIST_THREADS) void update_lds_kernel(const uint16_t
     };
     const int64_t bd = blockDim.x;
     int64_t i = r0 + threadIdx.x;
+    for (; i + 15 * bd < r1; i += 16 * bd) {
+        uint32_t bk[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) bk[u] = cj[i + u * bd] & bmask;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) add(bk[u]);
+    }
     for (; i + 3 * bd < r1; i += 4 * bd) {
         const uint32_t b0 = cj[i] & bmask, b1 = cj[i + bd] & bmask;
         const uint32_t b2 = cj[i + 2 * bd] & bmask, b3 = cj[i + 3 * bd] & bmask;
@@ -244,6 +252,13 @@ __global__ __launch_bounds__(HIST_THREADS) void update_table_kernel(const uint16
     };
     const int64_t bd = blockDim.x;
     int64_t i = threadIdx.x;
+    for (; i + 15 * bd < n; i += 16 * bd) {   // as in update_lds_kernel
+        uint32_t bk[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) bk[u] = cj[i + u * bd] & bmask;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) add(bk[u]);
+    }
     for (; i + 3 * bd < n; i += 4 * bd) {
         const uint32_t b0 = cj[i] & bmask, b1 = cj[i + bd] & bmask;
         const uint32_t b2 = cj[i + 2 * bd] & bmask, b3 = cj[i + 3 * bd] & bmask;
