@@ -61,9 +61,19 @@ __device__ inline void block_sum3(u64& a, u64& lo, u64& hi, u64* scratch) {
     }
 }
 
-// Exact change of (count^2, count^3) when a count moves from `old` by `delta`.
+// Exact change of (count^2, count^3) when a count moves from `old` by `delta`.  Counts
+// below 2^21 (cubes below 2^63, the usual case) take 64-bit products.
 __device__ inline void sq_cube_delta(int64_t old, int64_t delta, u64& d2, u64& d3lo, u64& d3hi) {
-    const i128 o = old, nw = old + delta;
+    const int64_t nw64 = old + delta;
+    if ((u64)old < ((u64)1 << 21) && (u64)nw64 < ((u64)1 << 21)) {
+        const int64_t o2 = old * old, n2 = nw64 * nw64;
+        const int64_t dd3 = n2 * nw64 - o2 * old;
+        d2 = (u64)(n2 - o2);
+        d3lo = (u64)dd3;
+        d3hi = dd3 < 0 ? ~0ull : 0ull;
+        return;
+    }
+    const i128 o = old, nw = nw64;
     const i128 dd2 = nw * nw - o * o;
     const i128 dd3 = nw * nw * nw - o * o * o;
     d2 = (u64)(int64_t)dd2;

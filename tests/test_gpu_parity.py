@@ -363,3 +363,41 @@ def test_score_matches_codes_path(K, L, bits, chunk):
     assert abs(ta["mu_scored"] - mu) <= 1e-12 * mu and abs(ta["sigma"] - sd) <= 1e-9 * sd
     a.close()
     b.close()
+
+
+def test_table_stats_past_2p21_counts():
+    """S2_j = sum_b A_j[b]^2 and S3_j = sum_b A_j[b]^3 (the exact sums behind mu and sigma_table,
+    Eq. dynadd / dynsub) when one bucket per table grows past 2^21 (its cube past 2^63:
+    the update's 128-bit branch) and shrinks back below it by deletion (Sec. 3.4.1), with
+    small buckets beside it: against Python integers from the counts."""
+    import torch
+    from paper_1706_06664_amd import ACE
+    K, L, d = 4, 3, 8
+    rng = np.random.default_rng(77)
+    W = projection_matrix(d, K, L, 77)
+    hot = rng.standard_normal((1, d)).astype(np.float32)
+    rest = rng.standard_normal((300_000, d)).astype(np.float32)
+    ace = ACE(W, K, L)
+    hot_d = torch.from_numpy(hot).cuda().expand(2_200_000, d).contiguous()
+
+    def check():
+        counts = ace.counts().astype(np.int64)
+        S2, S3 = ace.table_stats()
+        for j in range(L):
+            c = [int(v) for v in counts[j]]
+            assert int(S2[j]) == sum(v * v for v in c)
+            s3 = sum(v ** 3 for v in c)
+            assert int(S3[j][0]) | (int(S3[j][1]) << 64) == s3
+        return counts
+
+    ace.insert(torch.cat([hot_d[:1_500_000], torch.from_numpy(rest).cuda()]))
+    c1 = check()
+    assert (c1.max(axis=1) >= 1_500_000).all() and (c1.max(axis=1) < (1 << 21)).all()
+    ace.insert(hot_d[1_500_000:])
+    c2 = check()
+    assert (c2.max(axis=1) >= 2_200_000).all() and (c2.max(axis=1) > (1 << 21)).all()
+    ace.delete(hot_d[:500_000])
+    c3 = check()
+    assert (c3.max(axis=1) < (1 << 21)).all()
+    assert c3.sum() == L * 2_000_000
+    ace.close()
