@@ -179,8 +179,8 @@ def run_workload(Xd, W, K, L, precision, steps, warmup, refine=1, keep=None, cou
         ace.reset()
         ace.insert(Xd)
         ace.score(Xd, s=s, T=T)
-        th = ace.threshold("scored", 1.0)
-        return ace.flag(T, th["tau"], "scored"), th
+        flags, th = ace.threshold_flag(T, "scored", 1.0)   # threshold, then flags on the device
+        return flags, th
 
     for _ in range(warmup):
         step()
@@ -280,8 +280,7 @@ def cache_codes_run(Xd, W, K, L, steps, warmup):
         codes = ace.hash(Xd)
         ace.insert_codes(codes)
         _, T = ace.score_codes(codes)
-        th = ace.threshold("scored", 1.0)
-        return ace.flag(T, th["tau"], "scored")
+        return ace.threshold_flag(T, "scored", 1.0)[0]
 
     for _ in range(warmup):
         step()

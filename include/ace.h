@@ -202,6 +202,13 @@ ace_status ace_threshold(ace_ctx ctx, int32_t mode, double alpha, void* stream, 
 ace_status ace_flag(ace_ctx ctx, const uint32_t* T_dev, int64_t n, double tau, int32_t mode,
                     uint8_t* flags_dev, void* stream);
 
+/* ace_threshold followed by ace_flag with the tau it finds (Alg. 1 / Sec. 5.3 reporting),
+ * both enqueued on `stream` before the one wait, so the flags need no round trip through
+ * the host.  Fills *out as ace_threshold and flags_dev (uint8 [n]) as ace_flag.  If the
+ * mode's set is empty the call returns ACE_E_EMPTY and flags_dev is all zero. */
+ace_status ace_threshold_flag(ace_ctx ctx, int32_t mode, double alpha, const uint32_t* T_dev, int64_t n,
+                              uint8_t* flags_dev, void* stream, ace_thresh* out);
+
 /* The hash functions alone: the K*L signs of Sec. 2.1 concatenated into L K-bit codes
  * (Sec. 3.2).  codes_dev receives uint16 [L][n] (table-major: code of row i in table j at
  * j*n + i).  refined_dev (same shape, may be NULL) receives, per code, the mask of bits that

@@ -32,7 +32,7 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_debug_set_refine_queue", "ace_server_create", "ace_server_submit", "ace_server_wait",
            "ace_server_drain", "ace_server_replay", "ace_server_get_stats", "ace_server_reset_stats",
            "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe", "ace_hash_static", "ace_server_wait_for",
-           "ace_server_cancel", "ace_get_memory", "ace_server_debug_hold"]
+           "ace_server_cancel", "ace_get_memory", "ace_server_debug_hold", "ace_threshold_flag"]
 
 REQ_INSERT, REQ_SCORE = 0, 1
 SUBMIT_PINNED = 1
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "ace_score": [P, P, i64, P, P, P],
         "ace_threshold": [P, i32, f64, P, ctypes.POINTER(Thresh)],
         "ace_flag": [P, P, i64, f64, i32, P, P],
+        "ace_threshold_flag": [P, i32, f64, P, i64, P, P, ctypes.POINTER(Thresh)],
         "ace_hash": [P, P, i64, P, P, P],
         "ace_hash_static": [P, P, i64, P, P, P],
         "ace_insert_codes": [P, P, i64, P],
@@ -302,6 +303,18 @@ class ACE:
         _check(self.lib.ace_threshold(self.h, m, float(alpha), _stream_ptr(stream), ctypes.byref(out)),
                "ace_threshold")
         return {f: getattr(out, f) for f, _ in Thresh._fields_ if f != "pad"}
+
+    def threshold_flag(self, T, mode="scored", alpha: float = 1.0, stream=None):
+        """threshold() then flag() with its tau, enqueued together (one wait).  Returns
+        (flags, threshold dict)."""
+        import torch
+        m = _MODES[mode] if isinstance(mode, str) else int(mode)
+        flags = torch.empty(T.shape[0], dtype=torch.uint8, device=T.device)
+        out = Thresh()
+        _check(self.lib.ace_threshold_flag(self.h, m, float(alpha), _dev_ptr(T, torch.int32, "T"), T.shape[0],
+                                           flags.data_ptr(), _stream_ptr(stream), ctypes.byref(out)),
+               "ace_threshold_flag")
+        return flags, {f: getattr(out, f) for f, _ in Thresh._fields_ if f != "pad"}
 
     def flag(self, T, tau: float, mode="scored", stream=None):
         import torch

@@ -126,8 +126,8 @@ void free_all(ace_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     c->timed.clear();
     c->pool.clear();
-    void* ptrs[] = {c->Wt, c->wb, c->Wq, c->Wh, c->Wl, c->wbA, c->counts, c->S2, c->S3, c->mom, c->mpart, c->rcnt, c->err,
-                    c->sgn, c->sgn_lane};
+    void* ptrs[] = {c->Wt,  c->wb,  c->Wq,    c->Wh,   c->Wl,  c->wbA, c->counts,  c->S2, c->S3,
+                    c->mom, c->lim, c->mpart, c->rcnt, c->err, c->sgn, c->sgn_lane};
     ws_free(&c->ws);
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -499,6 +499,7 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
     st = st ? st : dev_alloc(c, (void**)&c->S2, sizeof(u64) * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->S3, sizeof(u64) * 2 * (size_t)L);
     st = st ? st : dev_alloc(c, (void**)&c->mom, sizeof(u64) * 4);
+    st = st ? st : dev_alloc(c, (void**)&c->lim, sizeof(double));
     // Per-block moments of a score launch over one workspace chunk (either score kernel).
     c->mpart_cap = (c->ws_rows + 255) / 256 + 1;
     st = st ? st : dev_alloc(c, (void**)&c->mpart, sizeof(u64) * 3 * (size_t)c->mpart_cap);
@@ -816,6 +817,39 @@ ace_status ace_threshold(ace_ctx c, int32_t mode, double alpha, void* stream, ac
         Bracket br(c, s, CLS_OTHER);
         st = check(c, launch_threshold(c->n_total, c->cfg.L, c->S2, c->S3, c->mom, c->err, mode, alpha, c->thr_dev,
                                        s));
+    }
+    if (st) return st;
+    if ((st = check(c, hipStreamSynchronize(s)))) return st;
+    const DevThresh r = *c->thr;
+    if (r.err) {
+        c->sticky = ACE_E_STATE;
+        return ACE_E_STATE;
+    }
+    out->n = r.n;
+    out->m_scored = r.m_scored;
+    out->mu = r.mu;
+    out->mu_scored = r.mu_scored;
+    out->sigma = r.sigma;
+    out->sigma_table = r.sigma_table;
+    out->tau = r.tau;
+    out->mode = r.mode;
+    out->pad = 0;
+    return r.status ? (ace_status)r.status : ACE_OK;
+}
+
+ace_status ace_threshold_flag(ace_ctx c, int32_t mode, double alpha, const uint32_t* T, int64_t n, uint8_t* flags,
+                              void* stream, ace_thresh* out) {
+    ace_status st = enter(c);
+    if (st) return st;
+    if (!out || mode < 0 || mode > 2 || !isfinite(alpha) || n < 0 || (n > 0 && (!T || !flags))) return ACE_E_INVALID;
+    if (take_injected_failure(c)) return ACE_E_DEVICE;
+    DeviceGuard g(c->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Bracket br(c, s, CLS_OTHER);
+        st = check(c, launch_threshold(c->n_total, c->cfg.L, c->S2, c->S3, c->mom, c->err, mode, alpha, c->thr_dev,
+                                       s, c->lim));
+        if (!st) st = check(c, launch_flags_dev(T, n, c->lim, mode, flags, s));
     }
     if (st) return st;
     if ((st = check(c, hipStreamSynchronize(s)))) return st;

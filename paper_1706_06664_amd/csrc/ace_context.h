@@ -56,6 +56,7 @@ struct ace_ctx_s {
     unsigned* err = nullptr;     // device error flags (1 = a count went below zero)
     ace::DevThresh* thr = nullptr;      // pinned host memory the threshold kernel writes
     ace::DevThresh* thr_dev = nullptr;  // its device address
+    double* lim = nullptr;              // L tau of the last threshold, for ace_threshold_flag
     ace::Workspace ws;             // workspace of the stream-ordered calls
     int64_t ws_rows = 0;           // rows per internal chunk
     ace::u64 list_cap = 0;              // queue entries used per chunk (<= allocated)

@@ -149,10 +149,13 @@ hipError_t launch_count_update(const uint16_t* codes, int64_t ldc, int64_t n, in
 hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, int L, const void* counts,
                         int counter_bits, float* s_out, uint32_t* T_out, u64* mom, hipStream_t s,
                         u64* mpart = nullptr, int64_t mpart_cap = 0);
-// out may be host memory mapped for the device (the result then needs no copy).
+// out may be host memory mapped for the device (the result then needs no copy).  lim (may
+// be null, device memory) receives L tau, the flag limit on T (NaN if the mode's set is empty).
 hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, const unsigned* err,
-                            int mode, double alpha, DevThresh* out, hipStream_t s);
+                            int mode, double alpha, DevThresh* out, hipStream_t s, double* lim = nullptr);
 hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mode, uint8_t* flags, hipStream_t s);
+// The same with the limit L tau read from device memory (written by launch_threshold).
+hipError_t launch_flags_dev(const uint32_t* T, int64_t n, const double* lim, int mode, uint8_t* flags, hipStream_t s);
 hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L, u64* S2, u64* S3, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Zero up to four small ranges of 64-bit words (each < 2^31 words; a null pointer with 0

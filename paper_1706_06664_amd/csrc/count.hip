@@ -493,7 +493,7 @@ __device__ inline double u128_to_double(u64 lo, u64 hi) {
 __global__ __launch_bounds__(256) void threshold_kernel(int64_t n, int L, const u64* __restrict__ S2,
                                                         const u64* __restrict__ S3, const u64* __restrict__ mom,
                                                         const unsigned* __restrict__ err, int mode, double alpha,
-                                                        DevThresh* __restrict__ out) {
+                                                        DevThresh* __restrict__ out, double* __restrict__ lim) {
     __shared__ u64 red[3 * 4];
     __shared__ double dsum[4];
     u64 s2lo = 0, s2hi = 0, unused = 0;
@@ -547,12 +547,24 @@ __global__ __launch_bounds__(256) void threshold_kernel(int64_t n, int L, const 
         else r.tau = r.mu - alpha * r.sigma_table;
     }
     *out = r;
+    if (lim) *lim = r.status ? __builtin_nan("") : (double)L * r.tau;
 }
 
 __global__ __launch_bounds__(256) void flags_kernel(const uint32_t* __restrict__ T, int64_t n, double lim, int le,
                                                     uint8_t* __restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double t = (double)T[i];
+    flags[i] = (uint8_t)(le ? (t <= lim) : (t < lim));
+}
+
+// flags_kernel with the limit in device memory (a NaN limit flags nothing).
+__global__ __launch_bounds__(256) void flags_dev_kernel(const uint32_t* __restrict__ T, int64_t n,
+                                                        const double* __restrict__ lim_p, int le,
+                                                        uint8_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double lim = *lim_p;
     const double t = (double)T[i];
     flags[i] = (uint8_t)(le ? (t <= lim) : (t < lim));
 }
@@ -702,8 +714,8 @@ hipError_t launch_score(const uint16_t* codes, int64_t ldc, int64_t n, int K, in
 }
 
 hipError_t launch_threshold(int64_t n, int L, const u64* S2, const u64* S3, const u64* mom, const unsigned* err,
-                            int mode, double alpha, DevThresh* out, hipStream_t s) {
-    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(256), 0, s, n, L, S2, S3, mom, err, mode, alpha, out);
+                            int mode, double alpha, DevThresh* out, hipStream_t s, double* lim) {
+    hipLaunchKernelGGL(threshold_kernel, dim3(1), dim3(256), 0, s, n, L, S2, S3, mom, err, mode, alpha, out, lim);
     return hipGetLastError();
 }
 
@@ -712,6 +724,14 @@ hipError_t launch_flags(const uint32_t* T, int64_t n, int L, double tau, int mod
     const int64_t nb = (n + 255) / 256;
     hipLaunchKernelGGL(flags_kernel, dim3((unsigned)nb), dim3(256), 0, s, T, n, (double)L * tau,
                        mode == ACE_THR_CONST ? 1 : 0, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_dev(const uint32_t* T, int64_t n, const double* lim, int mode, uint8_t* flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(flags_dev_kernel, dim3((unsigned)nb), dim3(256), 0, s, T, n, lim, mode == ACE_THR_CONST ? 1 : 0,
+                       flags);
     return hipGetLastError();
 }
 

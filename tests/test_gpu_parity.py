@@ -401,3 +401,39 @@ def test_table_stats_past_2p21_counts():
     assert (c3.max(axis=1) < (1 << 21)).all()
     assert c3.sum() == L * 2_000_000
     ace.close()
+
+
+def test_threshold_flag_matches_separate_calls():
+    """ace_threshold_flag (threshold and flags enqueued together, Alg. 1 / Sec. 5.3
+    reporting) against ace_threshold then ace_flag with the returned tau, in every mode; on
+    an empty set it returns ACE_E_EMPTY and flags nothing."""
+    import ctypes
+    import torch
+    from paper_1706_06664_amd import ACE, AceError
+    import paper_1706_06664_amd.ace as m
+    X, _ = gaussian_clusters(20_000, 24, 4, 0.05, seed=41)
+    K, L = 12, 20
+    W = projection_matrix(24, K, L, 41)
+    a = ACE(W, K, L)
+    Xd = torch.from_numpy(X).cuda()
+    a.insert(Xd)
+    _, T = a.score(Xd)
+    for mode in ("scored", "const", "table"):
+        th1 = a.threshold(mode, 1.0)
+        f1 = a.flag(T, th1["tau"], mode)
+        f2, th2 = a.threshold_flag(T, mode, 1.0)
+        assert th1 == th2
+        assert torch.equal(f1, f2)
+        assert 0 < int(f2.sum()) < T.shape[0]
+    b = ACE(W, K, L)
+    flags = torch.ones(T.shape[0], dtype=torch.uint8, device="cuda")
+    out = m.Thresh()
+    st = b.lib.ace_threshold_flag(b.h, m.THR_SCORED, 1.0, T.data_ptr(), T.shape[0], flags.data_ptr(), None,
+                                  ctypes.byref(out))
+    assert st == 4                                   # ACE_E_EMPTY
+    assert int(flags.sum()) == 0
+    with pytest.raises(AceError) as e:
+        b.threshold_flag(T, "const", 1.0)
+    assert e.value.status == 4
+    a.close()
+    b.close()
