@@ -679,9 +679,8 @@ ace_status ace_reset(ace_ctx c, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     Bracket br(c, s, CLS_OTHER);
     const size_t cb = (size_t)(c->cbits / 8) * (size_t)c->cfg.L << c->cfg.K;
-    st = check(c, launch_zero(c->counts, cb, s));
-    if (!st)
-        st = check(c, launch_zero_small(c->rcnt + 3, 1, c->S2, c->cfg.L, c->S3, 2 * (int64_t)c->cfg.L, c->mom, 4, s));
+    st = check(c, launch_zero_with_small(c->counts, cb, c->rcnt + 3, 1, c->S2, c->cfg.L, c->S3, 2 * (int64_t)c->cfg.L,
+                                         c->mom, 4, s));
     if (!st) c->n_total = 0;
     return st;
 }

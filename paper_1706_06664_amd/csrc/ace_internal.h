@@ -162,6 +162,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // words is skipped) in one launch.
 hipError_t launch_zero_small(u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2, int64_t w2, u64* p3, int64_t w3,
                              hipStream_t s);
+// launch_zero of p (bytes a multiple of 4) and launch_zero_small of the four ranges, in one launch.
+hipError_t launch_zero_with_small(void* p, size_t bytes, u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2,
+                                  int64_t w2, u64* p3, int64_t w3, hipStream_t s);
 // S[q] = sum_x p(q, x)^K (and S2[q] = sum_x p(q, x)^{2K} when S2 != nullptr); m >= 1.
 hipError_t launch_exact_score(const float* Q, int64_t m, const float* X, int64_t n, int d, int K, double* S,
                               double* S2, hipStream_t s);

@@ -745,6 +745,27 @@ hipError_t launch_table_sums(const void* counts, int counter_bits, int K, int L,
     return hipGetLastError();
 }
 
+// zero_kernel over p, and block 0 also clears the small ranges: one launch for both.
+__global__ __launch_bounds__(256) void zero_all_kernel(uint32_t* __restrict__ p, int64_t words, const ZeroRanges r) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+    if (blockIdx.x != 0) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int i = threadIdx.x; i < r.words[k]; i += blockDim.x) r.p[k][i] = 0ull;
+}
+
+hipError_t launch_zero_with_small(void* p, size_t bytes, u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2,
+                                  int64_t w2, u64* p3, int64_t w3, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 4);
+    int64_t nb = (words + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    ZeroRanges r{{p0, p1, p2, p3}, {(int32_t)w0, (int32_t)w1, (int32_t)w2, (int32_t)w3}};
+    hipLaunchKernelGGL(zero_all_kernel, dim3((unsigned)nb), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), words, r);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_small(u64* p0, int64_t w0, u64* p1, int64_t w1, u64* p2, int64_t w2, u64* p3, int64_t w3,
                              hipStream_t s) {
     ZeroRanges r{{p0, p1, p2, p3}, {(int32_t)w0, (int32_t)w1, (int32_t)w2, (int32_t)w3}};
