@@ -50,7 +50,7 @@ ace_status ws_alloc(ace_ctx c, Workspace* w, int64_t rows) {
     w->list_alloc = (u64)rows * (u64)L * KPAD / 32;
     if (w->list_alloc < 65536) w->list_alloc = 65536;
     st = st ? st : dev_alloc(c, (void**)&w->list, sizeof(u64) * (size_t)w->list_alloc);
-    st = st ? st : dev_alloc(c, (void**)&w->list_count, sizeof(u64));
+    st = st ? st : dev_alloc(c, (void**)&w->list_count, 2 * sizeof(u64));
     if (c->cfg.precision == ACE_BF16) {
         // whole 16-row tiles (the convert pass zeroes the rows past the chunk's last)
         const size_t rows16 = (size_t)(rows + 15) / 16 * 16;
@@ -221,8 +221,15 @@ int pick_tw(int L, bool fp32) {
 // [L][n]: projection + sign-pack, then the FP64 pass over the queued projections.
 ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, bool want_refined, hipStream_t s,
                            const int64_t* n_dev, bool count_bits) {
-    ace_status st = check(c, launch_zero(w->list_count, sizeof(u64), s));
-    if (st) return st;
+    // The queue counter: cleared here, or (a workspace that alternates two counters, with the
+    // FP64 pass on) already cleared by the previous chunk's FP64 pass.
+    const bool alt = w->cur >= 0 && c->cfg.refine == 1;
+    u64* const cnt = alt ? w->list_count + w->cur : w->list_count;
+    ace_status st = ACE_OK;
+    if (!alt) {
+        st = check(c, launch_zero(w->list_count, sizeof(u64), s));
+        if (st) return st;
+    }
     if (want_refined) {
         st = check(c, launch_zero(w->refined, sizeof(uint16_t) * ((size_t)c->cfg.L * n + 2), s));
         if (st) return st;
@@ -245,7 +252,7 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
     a.codes = w->codes;
     a.ldc = n;
     a.list = w->list;
-    a.list_count = w->list_count;
+    a.list_count = cnt;
     a.list_cap = c->list_cap < w->list_alloc ? c->list_cap : w->list_alloc;
     a.refined = want_refined ? w->refined : nullptr;
     a.counters = c->rcnt;
@@ -312,11 +319,14 @@ ace_status ace::hash_chunk(ace_ctx c, Workspace* w, const float* X, int64_t n, b
     r.ldc = n;
     r.refined = want_refined ? w->refined : nullptr;
     r.list = w->list;
-    r.list_count = w->list_count;
+    r.list_count = cnt;
     r.list_cap = a.list_cap;
     r.counters = c->rcnt;
+    r.clear_next = alt ? w->list_count + (w->cur ^ 1) : nullptr;
     Bracket br(c, s, CLS_REFINE, n);
-    return check(c, launch_refine(r, (int64_t)a.list_cap, vec, s));
+    st = check(c, launch_refine(r, (int64_t)a.list_cap, vec, s));
+    if (!st && alt) w->cur ^= 1;
+    return st;
 }
 
 namespace {
@@ -513,6 +523,9 @@ ace_status create_impl(const ace_config* cfg, const float* W_host, const uint8_t
         st = ACE_E_NOMEM;
     }
     st = st ? st : ws_alloc(c, &c->ws, c->ws_rows);
+    // The context's own workspace alternates its two queue counters (both start at zero).
+    if (!st) st = check(c, hipMemset(c->ws.list_count, 0, 2 * sizeof(u64)));
+    if (!st) c->ws.cur = 0;
     c->list_cap = c->ws.list_alloc;
     if (signs) {
         structured_shape(d, K, L, &c->dp, &c->nblk);

@@ -15,7 +15,10 @@ struct Workspace {
     uint16_t* codes = nullptr;     // [L][rows] (+ 2 elements of padding for the 32-bit patch atomics)
     uint16_t* refined = nullptr;   // same shape, allocated on first request
     u64* list = nullptr;           // queue of uncertain projections
-    u64* list_count = nullptr;
+    u64* list_count = nullptr;     // [2]: see cur
+    int cur = -1;                  // -1: list_count[0] is cleared by a launch before each projection;
+                                   // 0 / 1: the counter the next projection uses, the other one
+                                   // being cleared by the FP64 pass of the one before (refine = 1)
     u64 list_alloc = 0;
     uint16_t* xh = nullptr;        // [rows][DP] split-BF16 rows (BF16 precision)
     uint16_t* xl = nullptr;

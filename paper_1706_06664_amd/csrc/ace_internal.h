@@ -105,6 +105,7 @@ struct RefineArgs {
     const u64* list_count;
     u64 list_cap;
     u64* counters;         // [0] bits refined, [1] refined bits that flipped
+    u64* clear_next = nullptr;  // if set, zeroed: the queue counter of the next projection launch
 };
 
 // Mark bit cp (padded column) of row `row` in the refined mask, if one was asked for

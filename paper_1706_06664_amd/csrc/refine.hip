@@ -22,6 +22,7 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 template <bool VEC>
 __global__ __launch_bounds__(256) void refine_kernel(const RefineArgs a) {
     const u64 n_ent = min(*a.list_count, a.list_cap);
+    if (a.clear_next && blockIdx.x == 0 && threadIdx.x == 0) *a.clear_next = 0ull;
     uint32_t n_ref = 0, n_flip = 0;
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_ent; i += (u64)gridDim.x * blockDim.x) {
         const u64 e = a.list[i];
@@ -94,6 +95,7 @@ constexpr int RS = RC + 1;    // LDS row stride in floats (lane e reads row e: d
 __global__ __launch_bounds__(256, 2) void refine_staged_kernel(const RefineArgs a) {
     __shared__ float xs[4][64 * RS], ws[4][64 * RS];
     const u64 n_ent = min(*a.list_count, a.list_cap);
+    if (a.clear_next && blockIdx.x == 0 && threadIdx.x == 0) *a.clear_next = 0ull;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int d = a.d;
     float* xw = xs[wave];
