@@ -562,9 +562,9 @@ __global__ __launch_bounds__(256) void flags_kernel(const uint32_t* __restrict__
 __global__ __launch_bounds__(256) void flags_dev_kernel(const uint32_t* __restrict__ T, int64_t n,
                                                         const double* __restrict__ lim_p, int le,
                                                         uint8_t* __restrict__ flags) {
+    const double lim = *lim_p;   // read before the branch: one scalar load per wave
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double lim = *lim_p;
     const double t = (double)T[i];
     flags[i] = (uint8_t)(le ? (t <= lim) : (t < lim));
 }
