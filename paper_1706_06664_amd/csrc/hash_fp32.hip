@@ -531,6 +531,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
                     acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], bv[t], acc[b][t], 0, 0, 0);
         }
 
+        // This tile's column factors, loaded before the next tile's rows: memory waits
+        // count loads in issue order, so the epilogue's wait for these would otherwise also
+        // wait for the rows.
+        float wcol[TW];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
+
         // The next tile of this wave; the rows of its first k block are in flight during
         // the epilogue (the W^T block, an L2 hit, is loaded after it).
         int64_t v2 = v + gridDim.x, rbase2 = 0;
@@ -586,9 +593,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIRECT_WAVE
 #pragma unroll
             for (int b = 0; b < RB; ++b) ss[b] = (s0[b] + s1[b]) + (s2[b] + s3[b]);
         }
-        float wcol[TW];
-#pragma unroll
-        for (int t = 0; t < TW; ++t) wcol[t] = a.wb[cbase + 16 * t + cl];
         // Row bound factor gx * ||x||, rounded up by a relative 2^-20; lane cl holds it for
         // row 16b + cl, lane l needs rows 16b + 4 kin + r.  The four k groups' sums are added
         // in FP32 (two more roundings: d/4 + 5 in all, well inside norm_up), then the scaled
