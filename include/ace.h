@@ -333,21 +333,24 @@ ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
 
 /* ------------------------------------------------------------------------------------ */
 /* Serving loop: a request queue in front of one context (counting and query phases of
- * Alg. 1 arriving as a stream of row blocks).
+ * Alg. 1 arriving as a stream of row blocks, and deletions of rows inserted earlier,
+ * Sec. 3.4.1 Eq. dynsub, for a sliding window).
  *
  * Submission appends a request to a FIFO queue and returns.  A dispatcher thread batches
  * continuously: whenever one of `slots` slots is free, the longest prefix of the queue that
  * fits batch_rows rows (inserts and scores mixed; at least one request) becomes one batch.  Each slot has its own
  * HIP stream, hash workspace, device buffers of max_rows rows and pinned host staging.  A
  * batch runs, on its slot's stream: host-to-device copies of its rows, one hash of all of
- * them, then its count phase (a count update per run of consecutive inserts, a score per
- * run of consecutive scores) and a device-to-host copy of s and T.  A completion thread
+ * them, then its count phase (a count update per run of consecutive inserts, a decrement
+ * per run of consecutive deletes, a score per run of consecutive scores) and a
+ * device-to-host copy of s and T.  A completion thread
  * observes the slot's event, copies each request's outputs to the caller's buffers and
  * records its latency (from arrival to that observation).
  *
  * Ordering: the results equal those of running the requests one at a time in admission
  * order.  Hashes of different batches overlap; count phases run in admission order (each
- * waits on the previous batch's), so a score sees exactly the inserts admitted before it.
+ * waits on the previous batch's), so a score sees exactly the inserts and deletes admitted
+ * before it.
  * Scored rows join the context's scored set (as ace_score).
  *
  * While a server is attached, the context must not be used directly except after
@@ -355,7 +358,12 @@ ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
  * ace_destroy of the context returns ACE_E_STATE until ace_server_destroy. */
 typedef struct ace_server_s* ace_server;
 
-typedef enum { ACE_REQ_INSERT = 0, ACE_REQ_SCORE = 1 } ace_req_kind;
+/* ACE_REQ_DELETE removes rows inserted earlier (their counts go down by one, with exact
+ * S2/S3 updates, as ace_delete): a sliding window submits each insert's rows again as a
+ * delete once they leave the window.  The rows must be ones inserted before and not yet
+ * deleted; a bucket that would go below zero sets the context's underflow flag, which the
+ * next ace_threshold (after ace_server_drain) reports as ACE_E_STATE. */
+typedef enum { ACE_REQ_INSERT = 0, ACE_REQ_SCORE = 1, ACE_REQ_DELETE = 2 } ace_req_kind;
 
 /* Flag of ace_server_submit / ace_server_replay: the host rows are pinned memory
  * (hipHostMalloc).  If the request is at most gather_max_bytes and the runtime confirms
@@ -401,6 +409,8 @@ typedef struct {
     int64_t graph_launches, graph_captures;
     int64_t slots;                       /* slots the server holds (fewer than asked under mem_budget) */
     int64_t cancelled;                   /* requests cancelled before dispatch since the last reset */
+    int64_t deletes, delete_rows;        /* completed delete requests and their rows (not in inserts) */
+    double p99_delete_ms;
 } ace_server_stats;
 
 /* Create a server owning ctx's request stream.  Slots are allocated one after another
@@ -415,7 +425,8 @@ ace_status ace_server_create(ace_ctx ctx, const ace_server_config* cfg, ace_serv
  * (FP32 [n]) and T_host (uint32 [n]) host buffers, each may be NULL, are filled when the
  * request completes.  *ticket (may be NULL) identifies it for ace_server_wait.
  * ACE_E_INVALID for n outside 1..max_rows or a bad kind/flag; ACE_E_OVERFLOW as for
- * ace_insert / ace_score (counting every admitted insert); a device error is sticky on the
+ * ace_insert / ace_score (counting every admitted insert); ACE_E_STATE for a delete of more
+ * rows than the inserts admitted minus the deletes admitted; a device error is sticky on the
  * server: the failing batch, every later request and every later call report it. */
 ace_status ace_server_submit(ace_server srv, int32_t kind, const float* X_host, int64_t n, float* s_host,
                              uint32_t* T_host, int32_t flags, uint64_t* ticket);
@@ -432,7 +443,8 @@ ace_status ace_server_wait_for(ace_server srv, uint64_t ticket, double timeout_m
  * an insert does not count towards the points admitted, and later requests see the state
  * they would see had it never been submitted (the results equal those of the log without
  * it).  ACE_OK if it was withdrawn; ACE_E_STATE if it is already in a batch or complete
- * (then it runs to completion as usual); ACE_E_INVALID for an unknown ticket.  Waiting on a
+ * (then it runs to completion as usual), or if it is an insert whose rows the deletes
+ * admitted since would then outnumber; ACE_E_INVALID for an unknown ticket.  Waiting on a
  * withdrawn ticket returns ACE_E_STATE at once. */
 ace_status ace_server_cancel(ace_server srv, uint64_t ticket);
 

@@ -34,9 +34,9 @@ EXPORTS = ["ace_create", "ace_destroy", "ace_reset", "ace_reset_scored", "ace_in
            "ace_server_destroy", "ace_exact_score", "ace_create_structured", "ace_mfma_probe", "ace_hash_static", "ace_server_wait_for",
            "ace_server_cancel", "ace_get_memory", "ace_server_debug_hold", "ace_threshold_flag"]
 
-REQ_INSERT, REQ_SCORE = 0, 1
+REQ_INSERT, REQ_SCORE, REQ_DELETE = 0, 1, 2
 SUBMIT_PINNED = 1
-_KINDS = {"insert": REQ_INSERT, "score": REQ_SCORE}
+_KINDS = {"insert": REQ_INSERT, "score": REQ_SCORE, "delete": REQ_DELETE}
 
 # Layout of ace_request (one record per request of a replayed trace).
 REQUEST_DTYPE = np.dtype([("kind", "<i4"), ("pad", "<i4"), ("n", "<i8"), ("row0", "<i8"), ("out0", "<i8"),
@@ -91,7 +91,8 @@ class ServerStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("mean_batch_requests", ctypes.c_double),
                 ("gathered_requests", ctypes.c_int64), ("p50_queue_ms", ctypes.c_double),
                 ("p99_queue_ms", ctypes.c_double), ("graph_launches", ctypes.c_int64),
-                ("graph_captures", ctypes.c_int64), ("slots", ctypes.c_int64), ("cancelled", ctypes.c_int64)]
+                ("graph_captures", ctypes.c_int64), ("slots", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("deletes", ctypes.c_int64), ("delete_rows", ctypes.c_int64), ("p99_delete_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -413,7 +414,8 @@ def _host_ptr(a, dtype, what: str):
 
 class Server:
     """Serving loop of one ACE context: requests are admitted in order onto `slots`
-    streams; a score sees exactly the inserts admitted before it."""
+    streams; a score sees exactly the inserts and deletes admitted before it.  Kinds:
+    "insert", "score" and "delete" (rows inserted earlier leaving a sliding window)."""
 
     def __init__(self, ace: ACE, slots: int = 4, max_rows: int = 65536, gather_max_bytes: int = 0,
                  batch_rows: int = 0, graphs: bool = False):

@@ -1,13 +1,14 @@
 // Serving loop: a request queue in front of one ACE context.
 //
-// A request is a block of rows to insert (counting phase of Alg. 1) or to score (query
-// phase).  Submission appends it to a FIFO queue.  A dispatcher thread does continuous
+// A request is a block of rows to insert (counting phase of Alg. 1), to score (query
+// phase) or to delete (rows inserted earlier leaving a sliding window: Sec. 3.4.1,
+// Eq. dynsub).  Submission appends it to a FIFO queue.  A dispatcher thread does continuous
 // batching: whenever one of S slots is free it takes the longest prefix of the queue that
 // fits batch_rows rows (at least one request), inserts and scores mixed, as one batch.  Each slot owns a
 // HIP stream, the hash workspace, device buffers for a batch and pinned host staging.  On
 // its stream a batch runs host-to-device copies -> one hash of all its rows -> the count
-// phase: one count-update or score launch per run of consecutive same-kind requests, in
-// admission order -> device-to-host copy of s and T.  A completion thread polls the
+// phase: one count-update (increment or decrement) or score launch per run of consecutive
+// same-kind requests, in admission order -> device-to-host copy of s and T.  A completion thread polls the
 // events of busy slots, copies each request's outputs to the caller, records its latency
 // and frees the slot.  With use_graphs, the hash part of a batch is one hipGraph launch:
 // the pipeline (list reset, conversion, projection, FP64 pass) is captured once per slot and
@@ -18,7 +19,7 @@
 // Ordering.  Hashing reads only the rows and W, so hashes of different batches overlap
 // freely.  The count phase of a batch waits (hipStreamWaitEvent) on the count phase of the
 // batch dispatched before it, so count phases run in admission order and a score sees
-// exactly the inserts admitted before it, whatever S is: the results equal those of
+// exactly the inserts and deletes admitted before it, whatever S is: the results equal those of
 // running the requests one at a time in admission order.
 #include <hip/hip_runtime.h>
 
@@ -331,9 +332,9 @@ ace_status enqueue_batch(ace_server srv, Slot& sl, int64_t rows, hipEvent_t wait
         int64_t len = 0;
         for (; i < sl.reqs.size() && sl.reqs[i].kind == kind; ++i) len += sl.reqs[i].n;
         const uint16_t* codes = sl.ws.codes + off;   // table j of row r at codes[j * ldc + r]
-        if (kind == ACE_REQ_INSERT)
-            st = check(c, launch_count_update(codes, ldc, len, c->cfg.K, c->cfg.L, +1, c->counts, c->cbits, c->S2,
-                                              c->S3, c->err, c->rcnt + 3, sl.s));
+        if (kind == ACE_REQ_INSERT || kind == ACE_REQ_DELETE)
+            st = check(c, launch_count_update(codes, ldc, len, c->cfg.K, c->cfg.L, kind == ACE_REQ_INSERT ? +1 : -1,
+                                              c->counts, c->cbits, c->S2, c->S3, c->err, c->rcnt + 3, sl.s));
         else
             st = check(c, launch_score(codes, ldc, len, c->cfg.K, c->cfg.L, c->counts, c->cbits, sl.sd + off,
                                        sl.Td + off,
@@ -480,14 +481,16 @@ bool device_mapped_pinned(const float* X, size_t bytes) {
 ace_status submit_at(ace_server srv, int32_t kind, const float* X, int64_t n, float* s_host, uint32_t* T_host,
                      int32_t flags, Clock::time_point t_arrive, uint64_t* ticket, int gather = -1) {
     ace_ctx c = srv->c;
-    if (kind != ACE_REQ_INSERT && kind != ACE_REQ_SCORE) return ACE_E_INVALID;
+    if (kind != ACE_REQ_INSERT && kind != ACE_REQ_SCORE && kind != ACE_REQ_DELETE) return ACE_E_INVALID;
     if (n < 1 || n > srv->cfg.max_rows || !X) return ACE_E_INVALID;
     if (flags & ~ACE_SUBMIT_PINNED) return ACE_E_INVALID;
     std::lock_guard<std::mutex> sub(srv->submit_mu);
     std::unique_lock<std::mutex> lk(srv->mu);
     if (srv->err != ACE_OK) return srv->err;
-    // n_total counts every admitted insert, so the guards hold for any interleaving.
+    // n_total counts every admitted insert less every admitted delete, so the guards hold
+    // for any interleaving.
     if (kind == ACE_REQ_INSERT && c->n_total + n > c->cap) return ACE_E_OVERFLOW;
+    if (kind == ACE_REQ_DELETE && n > c->n_total) return ACE_E_STATE;
     if (kind == ACE_REQ_SCORE && c->cbits == 32 && (u64)c->cfg.L * (u64)c->n_total > 0xFFFFFFFFull)
         return ACE_E_OVERFLOW;
     if (c->fail_next) {
@@ -518,6 +521,7 @@ ace_status submit_at(ace_server srv, int32_t kind, const float* X, int64_t n, fl
     q.t_arrive = t_arrive;
     q.ticket = srv->next_ticket++;
     if (kind == ACE_REQ_INSERT) c->n_total += n;
+    if (kind == ACE_REQ_DELETE) c->n_total -= n;
     srv->latency_ms.push_back(-1.0);
     srv->queue_ms.push_back(-1.0);
     srv->done_of.push_back(0);
@@ -641,7 +645,12 @@ ace_status ace_server_cancel(ace_server srv, uint64_t ticket) {
         if (ticket >= srv->next_ticket) return ACE_E_INVALID;
         for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
             if (it->ticket != ticket) continue;
+            // Withdrawing an insert must not leave fewer points than the deletes admitted
+            // since; withdrawing a delete gives its rows back (within the insert cap).
+            if (it->kind == ACE_REQ_INSERT && srv->c->n_total < it->n) break;
+            if (it->kind == ACE_REQ_DELETE && srv->c->n_total + it->n > srv->c->cap) break;
             if (it->kind == ACE_REQ_INSERT) srv->c->n_total -= it->n;
+            if (it->kind == ACE_REQ_DELETE) srv->c->n_total += it->n;
             if (ticket >= srv->ticket_base) {
                 const size_t i = ticket - srv->ticket_base;
                 srv->done_of[i] = 2;
@@ -671,7 +680,7 @@ ace_status ace_server_replay(ace_server srv, const ace_request* reqs, int64_t nr
     if (pool_rows < 0 || (flags & ~ACE_SUBMIT_PINNED)) return ACE_E_INVALID;
     for (int64_t r = 0; r < nreq; ++r) {
         const ace_request& q = reqs[r];
-        if (q.kind != ACE_REQ_INSERT && q.kind != ACE_REQ_SCORE) return ACE_E_INVALID;
+        if (q.kind != ACE_REQ_INSERT && q.kind != ACE_REQ_SCORE && q.kind != ACE_REQ_DELETE) return ACE_E_INVALID;
         if (q.n < 1 || q.n > srv->cfg.max_rows || q.row0 < 0 || q.row0 > pool_rows - q.n) return ACE_E_INVALID;
         if (!(q.t_arrival_s >= 0)) return ACE_E_INVALID;
         if (q.kind == ACE_REQ_SCORE && (s_out || T_out) && q.out0 < 0) return ACE_E_INVALID;
@@ -711,19 +720,22 @@ ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     if (!srv || !out) return ACE_E_INVALID;
     std::lock_guard<std::mutex> lk(srv->mu);
     ace_server_stats s{};
-    std::vector<double> all, ins, sco, qw;
+    std::vector<double> all, ins, sco, del, qw;
     for (size_t i = 0; i < srv->latency_ms.size(); ++i) {
         if (!srv->done_of[i] || srv->latency_ms[i] < 0) continue;
         const double v = srv->latency_ms[i];
         all.push_back(v);
         qw.push_back(srv->queue_ms[i]);
-        (srv->kind_of[i] == ACE_REQ_INSERT ? ins : sco).push_back(v);
+        const int k = srv->kind_of[i];
+        (k == ACE_REQ_INSERT ? ins : k == ACE_REQ_DELETE ? del : sco).push_back(v);
         s.rows += srv->rows_of[i];
-        if (srv->kind_of[i] == ACE_REQ_INSERT) s.insert_rows += srv->rows_of[i];
+        if (k == ACE_REQ_INSERT) s.insert_rows += srv->rows_of[i];
+        if (k == ACE_REQ_DELETE) s.delete_rows += srv->rows_of[i];
     }
     s.requests = (int64_t)all.size();
     s.inserts = (int64_t)ins.size();
     s.scores = (int64_t)sco.size();
+    s.deletes = (int64_t)del.size();
     double sum = 0, mx = 0;
     for (double v : all) {
         sum += v;
@@ -735,6 +747,7 @@ ace_status ace_server_get_stats(ace_server srv, ace_server_stats* out) {
     s.p99_ms = percentile(all, 99.0);
     s.p99_insert_ms = percentile(ins, 99.0);
     s.p99_score_ms = percentile(sco, 99.0);
+    s.p99_delete_ms = percentile(del, 99.0);
     s.wall_ms = srv->have_first ? ms_between(srv->t_first, srv->t_last) : 0.0;
     s.batches = srv->batches;
     s.mean_batch_requests = srv->batches ? (double)srv->batched_requests / (double)srv->batches : 0.0;

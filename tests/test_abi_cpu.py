@@ -114,7 +114,36 @@ def test_request_record_layout_matches_header():
     assert [REQUEST_DTYPE.fields[f][1] for f in ("kind", "pad", "n", "row0", "out0", "t_arrival_s")] == \
         [0, 4, 8, 16, 24, 32]
     assert ctypes.sizeof(ServerConfig) == 32
-    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16 + 16 + 16
+    assert ctypes.sizeof(ServerStats) == 5 * 8 + 7 * 8 + 8 + 8 + 8 + 16 + 16 + 16 + 16 + 8
+
+
+def test_server_structs_match_header_offsets(tmp_path):
+    """The ctypes mirrors of ace_server_stats and ace_server_config against the header as a
+    C compiler lays it out (every field's offset, and the size)."""
+    import shutil
+    import subprocess
+    from paper_1706_06664_amd.ace import ServerConfig, ServerStats
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"ace_server_stats": ServerStats, "ace_server_config": ServerConfig}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ace.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_exact_score_rejects_bad_arguments():

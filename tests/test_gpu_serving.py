@@ -33,7 +33,8 @@ def _records(kind, n, row0, out0, t):
 
 
 def _oracle_replay(kind, n, row0, out0, pool, W, K, L):
-    """Sequential replay: hash every row once, then insert / score request by request."""
+    """Sequential replay: hash every row once, then insert / score / delete request by
+    request."""
     codes, amb = oracle.hash_codes(pool, W, K, L)
     sk = oracle.Sketch(K, L)
     T = np.zeros(int(n[kind == 1].sum()), np.int64)
@@ -41,9 +42,27 @@ def _oracle_replay(kind, n, row0, out0, pool, W, K, L):
         c = codes[row0[r]:row0[r] + n[r]]
         if kind[r] == 0:
             sk.insert_codes(c)
+        elif kind[r] == 2:
+            assert sk.delete_codes(c) == 0
         else:
             T[out0[r]:out0[r] + n[r]] = sk.score_codes(c)
     return T, sk, int(np.count_nonzero(amb))
+
+
+def _window_trace(nreq, d, window, seed):
+    """A serving trace with a sliding window: every insert's rows are deleted again once
+    `window` further requests of the trace have been admitted (Eq. dynsub)."""
+    kind, n, row0, out0, t, pool = serving_trace(nreq, d, seed=seed, median_batch=32, max_batch=1024)
+    k2, n2, r2, o2, due = [], [], [], [], []
+    for r in range(nreq):
+        k2.append(kind[r]); n2.append(n[r]); r2.append(row0[r]); o2.append(out0[r])
+        if kind[r] == 0:
+            due.append((r + window, n[r], row0[r]))
+        while due and due[0][0] <= r:
+            _, nn, rr = due.pop(0)
+            k2.append(2); n2.append(nn); r2.append(rr); o2.append(0)
+    return (np.array(k2, np.int32), np.array(n2, np.int64), np.array(r2, np.int64), np.array(o2, np.int64),
+            pool)
 
 
 @pytest.mark.parametrize("precision,d,slots,nreq,pinned,gmb,br,graphs", [
@@ -175,8 +194,12 @@ def test_server_errors():
         srv.submit("insert", X)
     assert e.value.status == 1
     with pytest.raises(AceError) as e:
-        srv.submit(2, X[:5])
+        srv.submit(3, X[:5])
     assert e.value.status == 1
+    # a delete of more rows than were inserted is refused at admission
+    with pytest.raises(AceError) as e:
+        srv.submit("delete", X[:5])
+    assert e.value.status == 6
     with pytest.raises(AceError) as e:
         srv.wait(12345)
     assert e.value.status == 1
@@ -193,6 +216,80 @@ def test_server_errors():
     srv2.drain()
     srv2.close()
     assert ace.threshold("const", 1.0)["n"] == 10
+    ace.close()
+
+
+@pytest.mark.parametrize("precision,d,slots,graphs", [
+    ("fp32", 64, 4, False), ("fp32", 61, 1, False), ("bf16", 256, 4, True), ("fp8", 256, 3, False)])
+def test_sliding_window_equals_sequential_replay(precision, d, slots, graphs):
+    """Inserts, scores and deletes of rows that leave a sliding window, all queued at once:
+    every score, the counts, n, mu and sigma equal the oracle replaying the log one request
+    at a time (deletes included), whatever the number of slots."""
+    from paper_1706_06664_amd import ACE
+    K, L = 15, 50
+    kind, n, row0, out0, pool = _window_trace(240, d, window=40, seed=8)
+    W = projection_matrix(d, K, L, 1706066646)
+    T_o, sk, n_amb = _oracle_replay(kind, n, row0, out0, pool, W, K, L)
+    assert n_amb == 0
+    nd = int((kind == 2).sum())
+    assert nd > 20 and int(n[kind == 2].sum()) < int(n[kind == 0].sum())
+    _say(dict(precision=precision, slots=slots, requests=len(kind), deletes=nd, scored=int(T_o.size)))
+    ace = ACE(W, K, L, precision=precision, refine=True)
+    srv = ace.server(slots=slots, max_rows=1024, graphs=graphs)
+    s_out = np.full(T_o.size, -1.0, np.float32)
+    T_out = np.zeros(T_o.size, np.uint32)
+    srv.replay(_records(kind, n, row0, out0, np.zeros(len(kind))), pool, s_out, T_out)
+    st = srv.stats()
+    _say(st)
+    assert st["requests"] == len(kind) and st["deletes"] == nd
+    assert st["delete_rows"] == int(n[kind == 2].sum()) and st["insert_rows"] == int(n[kind == 0].sum())
+    assert st["inserts"] + st["scores"] + st["deletes"] == len(kind)
+    np.testing.assert_array_equal(T_out.astype(np.int64), T_o)
+    np.testing.assert_allclose(s_out, T_o / L, rtol=1e-6, atol=0)
+    srv.close()
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    th = ace.threshold("scored", 1.0)
+    _, th_o = sk.threshold(oracle.MODE_SCORED, 1.0)
+    assert th["n"] == th_o["n"] == int(n[kind == 0].sum() - n[kind == 2].sum())
+    assert th["m_scored"] == th_o["m_scored"]
+    assert abs(th["mu"] - th_o["mu"]) <= 1e-12 * th_o["mu"]
+    assert abs(th["sigma"] - th_o["sigma"]) <= 1e-12 * max(th_o["sigma"], 1e-300)
+    ace.close()
+
+
+def test_cancel_with_deletes_keeps_counts_consistent():
+    """An insert cannot be withdrawn while a delete admitted after it still needs its rows;
+    once the delete is withdrawn it can, and nothing of either reaches the counts."""
+    from paper_1706_06664_amd import ACE, AceError
+    K, L, d = 10, 8, 32
+    W = projection_matrix(d, K, L, 14)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((10, d)).astype(np.float32)
+    B = rng.standard_normal((7, d)).astype(np.float32)
+    ace = ACE(W, K, L)
+    srv = ace.server(slots=2, max_rows=64)
+    tb = srv.submit("insert", B)
+    srv.drain()
+    srv.hold(True)
+    ta = srv.submit("insert", A)
+    td = srv.submit("delete", A)
+    with pytest.raises(AceError) as e:
+        srv.submit("delete", np.concatenate([B, B]))     # 14 > 7 + 10 - 10 points admitted
+    assert e.value.status == 6
+    assert srv.cancel(ta) is False                     # the delete still needs A's rows
+    assert srv.cancel(td) is True
+    assert srv.cancel(ta) is True
+    srv.hold(False)
+    srv.drain()
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["deletes"] == 0
+    srv.close()
+    codes, _ = oracle.hash_codes(B, W, K, L)
+    sk = oracle.Sketch(K, L)
+    sk.insert_codes(codes)
+    assert np.array_equal(ace.counts().astype(np.int64), sk.counts)
+    assert ace.threshold("const", 1.0)["n"] == 7
+    assert tb >= 0
     ace.close()
 
 
