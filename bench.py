@@ -486,11 +486,26 @@ def serving_log(n_req=100_000, d=256, seed=5):
             "n_req": n_req, "d": d}
 
 
-def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=False):
+def window_records(rec, window):
+    """The log with a sliding window: each insert's rows are deleted again (Eq. dynsub) right
+    after the request `window` places later, so at most the last `window` requests' inserts
+    stay counted."""
+    import numpy as np
+    n_req = len(rec)
+    ins = np.nonzero((rec["kind"] == 0) & (np.arange(n_req) + window < n_req))[0]
+    dels = rec[ins].copy()
+    dels["kind"], dels["out0"] = 2, 0
+    key = np.concatenate([2 * np.arange(n_req), 2 * (ins + window) + 1])
+    return np.concatenate([rec, dels])[np.argsort(key, kind="stable")]
+
+
+def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=False, window=None):
     """Serving workload: d = 256, K = 15, L = 50, the whole request log through the serving
     loop.  Closed loop (every request queued at once) gives the saturation rate in FP32 and
     BF16; open loop (Poisson arrivals at 0.5, 0.8 and 0.95 of the BF16 saturation request
-    rate) gives latency percentiles, from arrival to completion (host copies included)."""
+    rate) gives latency percentiles, from arrival to completion (host copies included).
+    window: also a closed-loop BF16 run of the log with a sliding window of that many
+    requests (every insert deleted again `window` requests later)."""
     import numpy as np
     import torch
     from ace_inputs import projection_matrix
@@ -501,7 +516,7 @@ def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=Fa
     s_out = torch.zeros(lg["scored"], dtype=torch.float32, pin_memory=lg["pinned"])
     T_out = torch.zeros(lg["scored"], dtype=torch.int32, pin_memory=lg["pinned"])
 
-    def run(prec, arr=None):
+    def run(prec, arr=None, recs=None):
         ace = ACE(W, K, L, precision=prec)
         srv = ace.server(slots=slots, max_rows=65_536, gather_max_bytes=gather_max_bytes, batch_rows=batch_rows,
                          graphs=graphs)
@@ -509,7 +524,7 @@ def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=Fa
         ace.reset()
         torch.cuda.synchronize()
         srv.reset_stats()
-        r = rec.copy()
+        r = (rec if recs is None else recs).copy()
         if arr is not None:
             r["t_arrival_s"] = arr
         srv.replay(r, pool, s_out, T_out, pinned=lg["pinned"])
@@ -518,6 +533,7 @@ def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=Fa
         ace.close()
         wall = st["wall_ms"] / 1e3
         return {"points_per_s": st["rows"] / wall, "requests_per_s": st["requests"] / wall,
+                "deletes": st["deletes"], "delete_rows": st["delete_rows"],
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "p99_queue_ms": st["p99_queue_ms"],
                 "max_ms": st["max_ms"], "batches": st["batches"],
                 "mean_batch_requests": st["mean_batch_requests"], "graph_launches": st["graph_launches"]}
@@ -530,6 +546,12 @@ def serving_runs(lg, slots=8, batch_rows=4096, gather_max_bytes=65536, graphs=Fa
         log(f"serving closed loop {prec}{' (graphs)' if graphs else ''}")
         out[f"closed_loop_{prec}"] = run(prec)
         log(f"  {out[f'closed_loop_{prec}']['points_per_s']:.3e} points/s")
+    if window:
+        log(f"serving closed loop bf16, sliding window of {window} requests")
+        out["closed_loop_bf16_window"] = run("bf16", recs=window_records(rec, window))
+        out["closed_loop_bf16_window"]["window_requests"] = window
+        log(f"  {out['closed_loop_bf16_window']['points_per_s']:.3e} points/s "
+            f"({out['closed_loop_bf16_window']['deletes']} deletes)")
     sat = out["closed_loop_bf16"]["requests_per_s"]
     out["open_loop_bf16"] = []
     base_rate = n_req / t[-1]
@@ -642,6 +664,9 @@ def workloads_block(extra):
                        "open_bf16": [{"load": o["load"], "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
                                       "pts_s": o["points_per_s"]} for o in sv["open_loop_bf16"]],
                        "requests": sv["workload"].split(": ")[1].split(",")[0],
+                       **({"bf16_window_pts_s": sv["closed_loop_bf16_window"]["points_per_s"],
+                           "window_requests": sv["closed_loop_bf16_window"]["window_requests"]}
+                          if "closed_loop_bf16_window" in sv else {}),
                        "rows": sv["workload"].split(": ")[1].split(", ")[1]}
     ex = extra.get("exact_score_connection_log")
     if ex:
@@ -735,7 +760,7 @@ def main():
         extra["low_rank_1024"] = low_rank_runs(args.low_rank_n, big_steps, big_warm, args.sample_rows)
         extra["heavy_tail_4096"] = heavy_tail_runs(big_steps, big_warm, args.sample_rows)
         lg = serving_log(args.serving_requests)
-        extra["serving_256"] = serving_runs(lg)
+        extra["serving_256"] = serving_runs(lg, window=10_000)
         extra["serving_256_graphs"] = serving_runs(lg, graphs=True)
         del lg
         torch.cuda.empty_cache()
