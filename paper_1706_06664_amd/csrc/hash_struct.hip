@@ -174,8 +174,8 @@ __global__ __launch_bounds__(256) void hash_struct_kernel(const HashArgs a) {
             const uint32_t* sg = a.sgn + (size_t)b * 3 * (dp / 32);
             const u64* sl = a.sgn_lane + (size_t)b * 3 * 64 + lane;   // bit r: element 64 r + lane
             if (TRANS) {
-                // round 1 (natural -> transposed), round 2 (transposed -> natural),
-                // round 3 (natural -> transposed), then back to the natural layout
+                // sign-and-transform pass 1 (natural -> transposed), pass 2 (transposed -> natural),
+                // pass 3 (natural -> transposed), then back to the natural layout
                 flip<R>(v, sl[0]);
                 reg_stages<R>(v);
                 transpose<R>(v, Tl, lane);
