@@ -338,7 +338,7 @@ ace_status ace_debug_set_refine_queue(ace_ctx ctx, int64_t entries);
  *
  * Submission appends a request to a FIFO queue and returns.  A dispatcher thread batches
  * continuously: whenever one of `slots` slots is free, the longest prefix of the queue that
- * fits batch_rows rows (inserts and scores mixed; at least one request) becomes one batch.  Each slot has its own
+ * fits batch_rows rows (inserts, scores and deletes mixed; at least one request) becomes one batch.  Each slot has its own
  * HIP stream, hash workspace, device buffers of max_rows rows and pinned host staging.  A
  * batch runs, on its slot's stream: host-to-device copies of its rows, one hash of all of
  * them, then its count phase (a count update per run of consecutive inserts, a decrement

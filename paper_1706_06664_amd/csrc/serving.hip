@@ -4,7 +4,7 @@
 // phase) or to delete (rows inserted earlier leaving a sliding window: Sec. 3.4.1,
 // Eq. dynsub).  Submission appends it to a FIFO queue.  A dispatcher thread does continuous
 // batching: whenever one of S slots is free it takes the longest prefix of the queue that
-// fits batch_rows rows (at least one request), inserts and scores mixed, as one batch.  Each slot owns a
+// fits batch_rows rows (at least one request), inserts, scores and deletes mixed, as one batch.  Each slot owns a
 // HIP stream, the hash workspace, device buffers for a batch and pinned host staging.  On
 // its stream a batch runs host-to-device copies -> one hash of all its rows -> the count
 // phase: one count-update (increment or decrement) or score launch per run of consecutive
