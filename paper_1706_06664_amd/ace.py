@@ -475,7 +475,8 @@ class Server:
 
     def cancel(self, ticket: int) -> bool:
         """Withdraw a request still in the queue: True if withdrawn, False if it already
-        runs or ran (it then completes as usual)."""
+        runs or ran (it then completes as usual), or if it is an insert whose rows the
+        deletes admitted since still need."""
         rc = self.lib.ace_server_cancel(self.h, int(ticket))
         if rc == 6:
             return False
